@@ -1,0 +1,271 @@
+"""ctypes front end of the C oracle plus the step drivers built on it.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Every function here
+is a thin call into bh_oracle.c or plain numpy bookkeeping around it; the
+arithmetic of the method lives in the C file.
+
+Stages (Iwasawa et al. 2019, Sec. 4.2 step (3) and Sec. 5.1):
+    keys -> sort -> tree -> moments -> groups -> lists -> forces
+and the kick-drift-kick integrator of step (4), with the list-reuse rule of
+Sec. 4.2: on a list-reusing step the tree topology, groups and lists are
+kept and only the node moments are recomputed from the current positions.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+__all__ = [
+    "lib", "keys", "sort_perm", "tree", "moments", "groups", "group_boxes",
+    "lists", "forces", "direct", "central", "bh_accel", "direct_accel",
+    "kdk", "n_threads",
+]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        src_m = os.path.getmtime(_build.SRC)
+        if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < src_m:
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        P = C.c_void_p
+        i64, i32, dbl = C.c_int64, C.c_int32, C.c_double
+        L.orc_keys.argtypes = [i64, P, P, P, P, P, P, P]
+        L.orc_keys.restype = C.c_int
+        L.orc_sort.argtypes = [i64, P, P]
+        L.orc_tree.argtypes = [i64, P, i32, i64, P, P, P, P, P, P]
+        L.orc_tree.restype = i64
+        L.orc_moments.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_groups.argtypes = [P, P, P, i32, i64, P]
+        L.orc_groups.restype = i64
+        L.orc_group_boxes.argtypes = [i64, P, P, P, P, P, P, P, P, P]
+        L.orc_lists.argtypes = [i64, P, P, P, P, P, dbl, P, P, P, P]
+        L.orc_forces.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P,
+                                 dbl, dbl, P, P, P, P, P]
+        L.orc_direct.argtypes = [i64, P, P, P, P, dbl, dbl, i64, P, P, P, P, P]
+        L.orc_central.argtypes = [i64, P, P, P, dbl, dbl, P, P, P]
+        L.orc_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def n_threads() -> int:
+    return int(lib().orc_threads())
+
+
+def keys(x, y, z):
+    """Root box and 63-bit keys.  Returns (lo[3], S, q[n,3] uint32, key uint64)."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    n = x.size
+    lo = np.zeros(3)
+    S = np.zeros(1)
+    q = np.zeros((n, 3), np.uint32)
+    k = np.zeros(n, np.uint64)
+    rc = lib().orc_keys(n, _p(x), _p(y), _p(z), _p(lo), _p(S), _p(q), _p(k))
+    if rc != 0:
+        raise ValueError("oracle keys: non-finite coordinate or empty input")
+    return lo, float(S[0]), q, k
+
+
+def sort_perm(key):
+    key = np.ascontiguousarray(key, np.uint64)
+    perm = np.zeros(key.size, np.uint32)
+    lib().orc_sort(key.size, _p(key), _p(perm))
+    return perm
+
+
+def tree(skey, n_leaf):
+    skey = np.ascontiguousarray(skey, np.uint64)
+    n = skey.size
+    cap = max(16, 2 * n + 64)
+    a = dict(level=np.zeros(cap, np.uint8), prefix=np.zeros(cap, np.uint64),
+             begin=np.zeros(cap, np.uint32), count=np.zeros(cap, np.uint32),
+             first_child=np.zeros(cap, np.uint32), n_child=np.zeros(cap, np.uint8))
+    nn = lib().orc_tree(n, _p(skey), int(n_leaf), cap, _p(a["level"]), _p(a["prefix"]),
+                        _p(a["begin"]), _p(a["count"]), _p(a["first_child"]), _p(a["n_child"]))
+    if nn < 0:
+        raise RuntimeError("oracle tree: node capacity exceeded")
+    return {k: v[:nn].copy() for k, v in a.items()}
+
+
+def moments(t, xs, ys, zs, ms, with_q=False):
+    nn = t["begin"].size
+    M, cx, cy, cz = (np.zeros(nn) for _ in range(4))
+    Q = np.zeros((nn, 6)) if with_q else None
+    xs, ys, zs, ms = _f64(xs), _f64(ys), _f64(zs), _f64(ms)
+    lib().orc_moments(nn, _p(t["begin"]), _p(t["count"]), _p(xs), _p(ys), _p(zs), _p(ms),
+                      _p(M), _p(cx), _p(cy), _p(cz), _p(Q))
+    out = dict(M=M, cx=cx, cy=cy, cz=cz)
+    if with_q:
+        out["Q"] = Q
+    return out
+
+
+def groups(t, n_grp):
+    cap = t["begin"].size
+    g = np.zeros(cap, np.uint32)
+    ng = lib().orc_groups(_p(t["count"]), _p(t["first_child"]), _p(t["n_child"]), int(n_grp), cap, _p(g))
+    if ng < 0:
+        raise RuntimeError("oracle groups: capacity exceeded")
+    return g[:ng].copy()
+
+
+def group_boxes(gnode, t, skey, xs, ys, zs):
+    ng = gnode.size
+    gbox = np.zeros((ng, 6), np.int32)
+    gcen = np.zeros((ng, 3))
+    skey = np.ascontiguousarray(skey, np.uint64)
+    xs, ys, zs = _f64(xs), _f64(ys), _f64(zs)
+    lib().orc_group_boxes(ng, _p(gnode), _p(t["begin"]), _p(t["count"]), _p(skey),
+                          _p(xs), _p(ys), _p(zs), _p(gbox), _p(gcen))
+    return gbox, gcen
+
+
+def lists(gbox, t, theta):
+    gbox = np.ascontiguousarray(gbox, np.int32)
+    ng = gbox.shape[0]
+    pc_off = np.zeros(ng + 1, np.int64)
+    pp_off = np.zeros(ng + 1, np.int64)
+    L = lib()
+    args = (_p(gbox), _p(t["level"]), _p(t["prefix"]), _p(t["first_child"]), _p(t["n_child"]),
+            float(theta))
+    L.orc_lists(ng, *args, _p(pc_off), _p(pp_off), None, None)
+    pc = np.zeros(max(1, int(pc_off[-1])), np.uint32)
+    pp = np.zeros(max(1, int(pp_off[-1])), np.uint32)
+    L.orc_lists(ng, *args, _p(pc_off), _p(pp_off), _p(pc), _p(pp))
+    return pc_off, pc[: pc_off[-1]].copy(), pp_off, pp[: pp_off[-1]].copy()
+
+
+def forces(gnode, t, xs, ys, zs, ms, mom, pc_off, pc, pp_off, pp, eps, G=1.0):
+    n = xs.size
+    ax, ay, az, pot, mag = (np.zeros(n) for _ in range(5))
+    xs, ys, zs, ms = _f64(xs), _f64(ys), _f64(zs), _f64(ms)
+    pc = np.ascontiguousarray(pc, np.uint32) if pc.size else np.zeros(1, np.uint32)
+    pp = np.ascontiguousarray(pp, np.uint32) if pp.size else np.zeros(1, np.uint32)
+    lib().orc_forces(gnode.size, _p(gnode), _p(t["begin"]), _p(t["count"]),
+                     _p(xs), _p(ys), _p(zs), _p(ms),
+                     _p(mom["M"]), _p(mom["cx"]), _p(mom["cy"]), _p(mom["cz"]),
+                     _p(pc_off), _p(pc), _p(pp_off), _p(pp), float(eps), float(G),
+                     _p(ax), _p(ay), _p(az), _p(pot), _p(mag))
+    return ax, ay, az, pot, mag
+
+
+def direct(x, y, z, m, eps, G=1.0, targets=None):
+    """O(N * n_targets) direct sum; returns (ax, ay, az, pot) per target."""
+    x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
+    tg = None if targets is None else np.ascontiguousarray(targets, np.int64)
+    nt = x.size if tg is None else tg.size
+    ax, ay, az, pot = (np.zeros(nt) for _ in range(4))
+    lib().orc_direct(x.size, _p(x), _p(y), _p(z), _p(m), float(eps), float(G), nt, _p(tg),
+                     _p(ax), _p(ay), _p(az), _p(pot))
+    return ax, ay, az, pot
+
+
+def central(x, y, z, Mc, G, ax, ay, az):
+    """Adds the external point mass at the origin to (ax, ay, az) in place."""
+    lib().orc_central(x.size, _p(_f64(x)), _p(_f64(y)), _p(_f64(z)), float(Mc), float(G),
+                      _p(ax), _p(ay), _p(az))
+
+
+class BHState:
+    """Tree, groups and lists of one build, kept for list-reusing steps."""
+
+    def __init__(self, x, y, z, m, theta, n_leaf, n_grp, with_q=False):
+        self.lo, self.S, _, key = keys(x, y, z)
+        self.perm = sort_perm(key)
+        self.skey = key[self.perm]
+        self.tree = tree(self.skey, n_leaf)
+        xs, ys, zs, ms = (np.asarray(a)[self.perm] for a in (x, y, z, m))
+        self.mom = moments(self.tree, xs, ys, zs, ms, with_q)
+        self.gnode = groups(self.tree, n_grp)
+        self.gbox, self.gcen = group_boxes(self.gnode, self.tree, self.skey, xs, ys, zs)
+        self.pc_off, self.pc, self.pp_off, self.pp = lists(self.gbox, self.tree, theta)
+
+    def refresh(self, x, y, z, m):
+        """List-reusing step: same topology, moments from the current positions."""
+        xs, ys, zs, ms = (np.asarray(a)[self.perm] for a in (x, y, z, m))
+        self.mom = moments(self.tree, xs, ys, zs, ms, "Q" in self.mom)
+
+    def accel(self, x, y, z, m, eps, G=1.0):
+        xs, ys, zs, ms = (np.asarray(a)[self.perm] for a in (x, y, z, m))
+        ax, ay, az, pot, mag = forces(self.gnode, self.tree, xs, ys, zs, ms, self.mom,
+                                      self.pc_off, self.pc, self.pp_off, self.pp, eps, G)
+        out = [np.empty_like(ax) for _ in range(5)]
+        for o, a in zip(out, (ax, ay, az, pot, mag)):
+            o[self.perm] = a
+        return tuple(out)
+
+    def interactions(self):
+        """Pairs evaluated: sum over groups of n_g * (particles in pp leaves + pc cells)."""
+        cnt = self.tree["count"]
+        ng = cnt[self.gnode].astype(np.int64)
+        pp_len = np.add.reduceat(cnt[self.pp].astype(np.int64), self.pp_off[:-1]) if self.pp.size else 0
+        pp_len = np.where(np.diff(self.pp_off) > 0, pp_len, 0)
+        pc_len = np.diff(self.pc_off)
+        return int(np.sum(ng * (pp_len + pc_len)))
+
+
+def bh_accel(x, y, z, m, theta, eps, n_leaf=8, n_grp=64, G=1.0):
+    """Full Barnes-Hut force in caller order: (ax, ay, az, pot, magsum, state)."""
+    st = BHState(x, y, z, m, theta, n_leaf, n_grp)
+    return (*st.accel(x, y, z, m, eps, G), st)
+
+
+def direct_accel(x, y, z, m, eps, G=1.0):
+    ax, ay, az, pot = direct(x, y, z, m, eps, G)
+    return ax, ay, az, pot
+
+
+def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
+        theta=None, n_leaf=8, n_grp=64, rebuild_every=1):
+    """Kick-drift-kick leapfrog in FP64 (the integration step (4) of Sec. 4.2).
+
+    theta=None uses the direct sum; otherwise Barnes-Hut with lists rebuilt
+    every `rebuild_every` steps and moments refreshed on the other steps.
+    Returns new copies of (x, y, z, vx, vy, vz).
+    """
+    x, y, z, vx, vy, vz = (np.array(a, dtype=np.float64, copy=True) for a in (x, y, z, vx, vy, vz))
+    m = _f64(m)
+    state = None
+
+    def acc(step):
+        nonlocal state
+        if theta is None:
+            ax, ay, az, _ = direct(x, y, z, m, eps, G)
+        else:
+            if state is None or step % rebuild_every == 0:
+                state = BHState(x, y, z, m, theta, n_leaf, n_grp)
+            else:
+                state.refresh(x, y, z, m)
+            ax, ay, az, _, _ = state.accel(x, y, z, m, eps, G)
+        if central_mass:
+            central(x, y, z, central_mass, G, ax, ay, az)
+        return ax, ay, az
+
+    ax, ay, az = acc(0)
+    h = 0.5 * dt
+    for k in range(n_steps):
+        vx += h * ax
+        vy += h * ay
+        vz += h * az
+        x += dt * vx
+        y += dt * vy
+        z += dt * vz
+        ax, ay, az = acc(k + 1)
+        vx += h * ax
+        vy += h * ay
+        vz += h * az
+    return x, y, z, vx, vy, vz
