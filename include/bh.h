@@ -1,0 +1,190 @@
+/*
+ * bh.h -- C ABI of the Barnes-Hut gravity library for one MI355X (gfx950).
+ *
+ * The calls follow the steps of one timestep of a self-gravitating particle
+ * code as Iwasawa et al. (2019), Sec. 4.2, lists them for one domain:
+ *   bh_build_tree   step (3a)/(3c): keys, sort, octree and node moments
+ *   bh_make_lists   step (3d), first half: per-group tree walk that writes
+ *                   the group's particle list and node list
+ *   bh_forces       step (3d), second half: double loop over the group's
+ *                   particles and its list, with the gravity branch of
+ *                   Eq. (2) softened by a Plummer eps, nodes as point
+ *                   masses at their centre of mass (Sec. 5.1)
+ *   bh_step         step (4) plus the persistent interaction list of
+ *                   Sec. 4.2: lists are kept for `rebuild_every` steps while
+ *                   node moments are recomputed from the moved particles
+ *                   every step.  The integrator runs inside the library, next
+ *                   to the particle data (Sec. 6.1).
+ *
+ * Memory and ownership
+ *   - Particle arrays (bh_system) are DEVICE pointers owned by the caller,
+ *     FP64, structure-of-arrays, one entry per particle in the caller's
+ *     order.  The library never keeps a caller pointer past the call.
+ *   - The context owns every derived structure (sorted copy of the
+ *     particles, keys, tree, groups, lists, scratch) in device memory it
+ *     allocates itself.  bh_destroy frees it.
+ *   - `stream` is a hipStream_t (passed as void*); all device work of a call
+ *     is enqueued on it.  bh_build_tree, bh_make_lists and bh_step
+ *     synchronise that stream once per tree build to read back sizes and
+ *     error flags; bh_forces does not synchronise.
+ *
+ * Errors
+ *   Every call returns a bh_status and never throws.  On failure the context
+ *   keeps a message readable with bh_last_error.  Non-finite coordinates or
+ *   an empty system give BH_EINVAL.  Calls out of order (bh_forces before
+ *   bh_make_lists) give BH_ESTATE.  Internal buffers that turn out too small
+ *   are grown and the stage redone; BH_ENOMEM is returned only when the
+ *   device allocation itself fails.  A HIP runtime error gives BH_EHIP.
+ *
+ * Several independent systems may be handled by one context (one call, one
+ * launch per stage); each keeps its own root cell, tree and lists.
+ */
+#ifndef BH_H
+#define BH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bh_ctx bh_ctx;
+
+typedef enum {
+    BH_OK = 0,
+    BH_EINVAL = -1,
+    BH_ENOMEM = -2,
+    BH_EHIP = -3,
+    BH_ESTATE = -4,
+    BH_ECAPACITY = -5
+} bh_status;
+
+/* Arithmetic of the interaction loop.  BH_FP32_REL: positions of the
+ * group's particles and of its sources are taken relative to the group
+ * centre in FP64, rounded to FP32, and the pair terms are evaluated and
+ * summed in FP32 (the shifted-origin single-precision kernel of Sec. 4.7);
+ * positions, moments and the integrator stay FP64. */
+typedef enum { BH_FP64 = 0, BH_FP32_REL = 1 } bh_precision;
+
+/* Opening rule of the walk.  GEOMETRIC: a node of side s is accepted for a
+ * group when it lies outside the group's box and s < theta * d, d the
+ * distance from the node's centre to the box.  LEARNED: inside the band
+ * theta_min <= s/d < theta_max a small network predicts the node's monopole
+ * error and the node is accepted when the prediction is below tau times the
+ * group's smallest acceleration; outside the band the geometric rule holds. */
+typedef enum { BH_OPEN_GEOMETRIC = 0, BH_OPEN_LEARNED = 1 } bh_criterion;
+
+typedef struct {
+    double theta;          /* opening angle, >= 0 */
+    double eps;            /* Plummer softening length, >= 0 */
+    double G;              /* gravitational constant */
+    double central_mass;   /* point mass fixed at the origin, 0 = none; not part of the tree */
+    int32_t n_leaf;        /* a node with more particles than this is split (>= 1) */
+    int32_t n_group;       /* largest group; <= 0 lets the autotuner choose */
+    int32_t precision;     /* bh_precision */
+    int32_t criterion;     /* bh_criterion */
+    double theta_min, theta_max, tau;   /* learned rule only */
+} bh_params;
+
+/* One system: device arrays of n FP64 values each, caller order.
+ * bh_step updates x,y,z,vx,vy,vz in place; m is read only. */
+typedef struct {
+    int64_t n;
+    double *x, *y, *z;
+    double *vx, *vy, *vz;
+    const double *m;
+} bh_system;
+
+/* Output of bh_forces for one system: device arrays of n FP64 values,
+ * caller order.  pot may be NULL. */
+typedef struct {
+    double *ax, *ay, *az, *pot;
+} bh_accel;
+
+typedef struct {
+    int64_t n_particles;      /* over all systems */
+    int32_t n_systems;
+    int32_t max_level;        /* deepest tree level */
+    int64_t n_nodes;
+    int64_t n_groups;
+    int64_t n_pc;             /* node-list entries over all groups */
+    int64_t n_pp;             /* particle-list entries (leaves) over all groups */
+    int64_t interactions;     /* sum over groups of n_g * (particles in pp leaves + pc nodes) */
+    int32_t n_group_used;     /* group size in effect */
+    int32_t lists_valid;      /* 1 once bh_make_lists has run on the current tree */
+} bh_sizes;
+
+/* What bh_export copies out (to HOST memory; the call synchronises `stream`).
+ * Sizes come from bh_query.  Node ids are global over all systems and
+ * ordered by (level, system, key prefix). */
+typedef enum {
+    BH_EXPORT_KEYS = 0,       /* uint64[n_particles]  keys in sorted order */
+    BH_EXPORT_PERM = 1,       /* uint32[n_particles]  sorted slot -> caller index within its system */
+    BH_EXPORT_NODES = 2,      /* per node, int64[n_nodes][8]: level, system, prefix, begin,
+                                 count, first_child, n_child, is_group */
+    BH_EXPORT_MOMENTS = 3,    /* double[n_nodes][4]: com x, y, z, mass */
+    BH_EXPORT_GROUPS = 4,     /* per group, int64[n_groups][8]: node, begin, count, box lo xyz,
+                                 plus box hi xyz in a second block: see bh_export_groups */
+    BH_EXPORT_LISTS = 5,      /* CSR: int64 pc_off[n_groups+1], int64 pp_off[n_groups+1],
+                                 uint32 pc[n_pc], uint32 pp[n_pp], packed in that order,
+                                 each list in ascending node id */
+    BH_EXPORT_ACC_SORTED = 6, /* double[n_particles][4]: ax, ay, az, pot in sorted order */
+    BH_EXPORT_SORTED_POS = 7  /* double[n_particles][4]: x, y, z, m in sorted order */
+} bh_what;
+
+/* Create a context.  p is copied.  BH_EINVAL for out-of-range parameters. */
+bh_status bh_create(bh_ctx **out, const bh_params *p);
+/* Free the context and all its device memory (synchronises the device). */
+bh_status bh_destroy(bh_ctx *ctx);
+/* Replace the parameters; invalidates lists.  theta and n_group changes need
+ * bh_make_lists (and, for n_group, bh_build_tree) again. */
+bh_status bh_set_params(bh_ctx *ctx, const bh_params *p);
+
+/* Sec. 4.2 (3a): root box, keys, sort and permutation, octree, node
+ * moments, groups, for n_sys systems (sys[0..n_sys-1] host array of device
+ * pointer sets).  Keeps a sorted FP64 copy of positions, velocities and
+ * masses.  Invalidates lists. */
+bh_status bh_build_tree(bh_ctx *ctx, const bh_system *sys, int32_t n_sys, void *stream);
+
+/* Sec. 4.2 (3d): walk the tree once per group and store its node list and
+ * particle list.  Requires bh_build_tree. */
+bh_status bh_make_lists(bh_ctx *ctx, void *stream);
+
+/* Sec. 4.2 (3d) and Eq. (2): accelerations (and optionally potentials) of
+ * every particle from its group's lists, written in caller order into
+ * out[0..n_sys-1] (host array of device pointer sets).  out may be NULL to
+ * keep the result only inside the context (bh_export ACC_SORTED).
+ * Requires bh_make_lists.  Does not synchronise. */
+bh_status bh_forces(bh_ctx *ctx, const bh_accel *out, void *stream);
+
+/* Step (4) with the persistent interaction list: n_steps kick-drift-kick
+ * steps of size dt.  The tree and lists are built at the start and rebuilt
+ * before the force evaluation of every step whose index (1-based, counted
+ * from the start of this call) is a multiple of rebuild_every; on the other
+ * steps node moments are recomputed with the same tree and lists.  Reuse
+ * steps are replayed from a captured HIP graph.  x, y, z, vx, vy, vz of
+ * every system are updated in place. */
+bh_status bh_step(bh_ctx *ctx, const bh_system *sys, int32_t n_sys, double dt,
+                  int32_t n_steps, int32_t rebuild_every, void *stream);
+
+bh_status bh_query(const bh_ctx *ctx, bh_sizes *out);
+
+/* Copy one internal structure to host memory dst (layouts in bh_what). */
+bh_status bh_export(bh_ctx *ctx, int32_t what, void *dst, void *stream);
+
+/* Group boxes: int32[n_groups][6] grid box lo xyz, hi xyz (half-open) and
+ * double[n_groups][3] centres; either pointer may be NULL. */
+bh_status bh_export_groups(bh_ctx *ctx, int32_t *box, double *centre, void *stream);
+
+/* Per-stage device times in milliseconds of the last call of each kind,
+ * measured with HIP events on the call's stream:
+ * [0] keys+sort+permute, [1] tree, [2] moments, [3] groups, [4] walk,
+ * [5] forces (force kernel only), [6] integrate, [7] whole last bh_step. */
+bh_status bh_stage_times(bh_ctx *ctx, double *ms8);
+
+const char *bh_last_error(const bh_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BH_H */

@@ -20,7 +20,7 @@ from . import build as _build
 __all__ = [
     "lib", "keys", "sort_perm", "tree", "moments", "groups", "group_boxes",
     "lists", "forces", "direct", "central", "bh_accel", "direct_accel",
-    "kdk", "n_threads",
+    "kdk", "n_threads", "BHState",
 ]
 
 _lib = None

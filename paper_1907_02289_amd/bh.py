@@ -1,0 +1,215 @@
+"""ctypes binding of libbh.so (include/bh.h).
+
+Argument marshalling only: every step of the Barnes-Hut path runs in the HIP
+kernels of the library.  PyTorch provides device memory (tensors' data
+pointers) and the stream (torch.cuda.current_stream()).  If the library is
+not built, loading fails with an error: there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbh.so")
+
+BH_OK, BH_EINVAL, BH_ENOMEM, BH_EHIP, BH_ESTATE, BH_ECAPACITY = 0, -1, -2, -3, -4, -5
+FP64, FP32_REL = 0, 1
+GEOMETRIC, LEARNED = 0, 1
+EXPORT = dict(keys=0, perm=1, nodes=2, moments=3, groups=4, lists=5, acc_sorted=6, sorted_pos=7)
+STAGES = ("keys_sort", "tree", "moments", "groups", "walk", "forces", "integrate", "step")
+
+SYMBOLS = ("bh_create", "bh_destroy", "bh_set_params", "bh_build_tree", "bh_make_lists", "bh_forces",
+           "bh_step", "bh_query", "bh_export", "bh_export_groups", "bh_stage_times", "bh_last_error")
+
+
+class Params(C.Structure):
+    _fields_ = [("theta", C.c_double), ("eps", C.c_double), ("G", C.c_double), ("central_mass", C.c_double),
+                ("n_leaf", C.c_int32), ("n_group", C.c_int32), ("precision", C.c_int32),
+                ("criterion", C.c_int32), ("theta_min", C.c_double), ("theta_max", C.c_double),
+                ("tau", C.c_double)]
+
+
+class System(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(k, C.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz", "m")]
+
+
+class Accel(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("ax", "ay", "az", "pot")]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("n_particles", C.c_int64), ("n_systems", C.c_int32), ("max_level", C.c_int32),
+                ("n_nodes", C.c_int64), ("n_groups", C.c_int64), ("n_pc", C.c_int64), ("n_pp", C.c_int64),
+                ("interactions", C.c_int64), ("n_group_used", C.c_int32), ("lists_valid", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libbh.so.  torch is imported first so that the library binds to
+    the HIP runtime torch already loaded (same SONAME)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run python -m paper_1907_02289_amd.build")
+    L = C.CDLL(path)
+    vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+    L.bh_create.argtypes = [C.POINTER(vp), C.POINTER(Params)]
+    L.bh_destroy.argtypes = [vp]
+    L.bh_set_params.argtypes = [vp, C.POINTER(Params)]
+    L.bh_build_tree.argtypes = [vp, C.POINTER(System), i32, vp]
+    L.bh_make_lists.argtypes = [vp, vp]
+    L.bh_forces.argtypes = [vp, C.POINTER(Accel), vp]
+    L.bh_step.argtypes = [vp, C.POINTER(System), i32, dbl, i32, i32, vp]
+    L.bh_query.argtypes = [vp, C.POINTER(Sizes)]
+    L.bh_export.argtypes = [vp, i32, vp, vp]
+    L.bh_export_groups.argtypes = [vp, vp, vp, vp]
+    L.bh_stage_times.argtypes = [vp, C.POINTER(C.c_double)]
+    L.bh_last_error.argtypes = [vp]
+    L.bh_last_error.restype = C.c_char_p
+    for name in SYMBOLS:
+        if name != "bh_last_error":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+class BHError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"bh status {status}: {msg}")
+        self.status = status
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.dtype.is_floating_point and t.is_contiguous(), "need contiguous CUDA FP64 tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One library context (tree, lists and scratch on the current device)."""
+
+    def __init__(self, theta=0.5, eps=1e-3, G=1.0, central_mass=0.0, n_leaf=8, n_group=64,
+                 precision=FP64, criterion=GEOMETRIC, theta_min=0.2, theta_max=1.0, tau=1e-3):
+        self.L = load_library()
+        self.params = Params(theta, eps, G, central_mass, n_leaf, n_group, precision, criterion,
+                             theta_min, theta_max, tau)
+        h = C.c_void_p()
+        self._check(self.L.bh_create(C.byref(h), C.byref(self.params)), ctx=None)
+        self.h = h
+        self._keep = []
+
+    def _check(self, st, ctx="self"):
+        if st != BH_OK:
+            msg = self.L.bh_last_error(self.h).decode() if ctx is not None and getattr(self, "h", None) else ""
+            raise BHError(st, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.bh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, **kw):
+        for k, v in kw.items():
+            setattr(self.params, k, v)
+        self._check(self.L.bh_set_params(self.h, C.byref(self.params)))
+
+    @staticmethod
+    def _systems(systems):
+        arr = (System * len(systems))()
+        for k, s in enumerate(systems):
+            arr[k].n = s["x"].numel()
+            for f in ("x", "y", "z", "vx", "vy", "vz", "m"):
+                setattr(arr[k], f, _ptr(s.get(f)))
+        return arr
+
+    def build_tree(self, systems):
+        arr = self._systems(systems)
+        self._check(self.L.bh_build_tree(self.h, arr, len(systems), _stream()))
+
+    def make_lists(self):
+        self._check(self.L.bh_make_lists(self.h, _stream()))
+
+    def forces(self, outs=None):
+        """outs: list (one per system) of dicts with ax, ay, az[, pot] tensors, or None."""
+        if outs is None:
+            self._check(self.L.bh_forces(self.h, None, _stream()))
+            return
+        arr = (Accel * len(outs))()
+        for k, o in enumerate(outs):
+            for f in ("ax", "ay", "az", "pot"):
+                setattr(arr[k], f, _ptr(o.get(f)))
+        self._check(self.L.bh_forces(self.h, arr, _stream()))
+
+    def step(self, systems, dt, n_steps, rebuild_every=1):
+        arr = self._systems(systems)
+        self._check(self.L.bh_step(self.h, arr, len(systems), float(dt), int(n_steps), int(rebuild_every),
+                                   _stream()))
+
+    def query(self):
+        s = Sizes()
+        self._check(self.L.bh_query(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in Sizes._fields_}
+
+    def export(self, what):
+        q = self.query()
+        n, nn, ng = q["n_particles"], q["n_nodes"], q["n_groups"]
+        if what == "keys":
+            out = np.zeros(n, np.uint64)
+        elif what == "perm":
+            out = np.zeros(n, np.uint32)
+        elif what == "nodes":
+            out = np.zeros((nn, 8), np.int64)
+        elif what == "moments":
+            out = np.zeros((nn, 4))
+        elif what == "groups":
+            out = np.zeros((ng, 4), np.int64)
+        elif what in ("acc_sorted", "sorted_pos"):
+            out = np.zeros((n, 4))
+        elif what == "lists":
+            npc, npp = q["n_pc"], q["n_pp"]
+            raw = np.zeros(2 * (ng + 1) * 8 + 4 * (npc + npp) + 8, np.uint8)
+            self._check(self.L.bh_export(self.h, EXPORT[what], raw.ctypes.data_as(C.c_void_p), _stream()))
+            off = raw[: 2 * (ng + 1) * 8].view(np.int64)
+            ids = raw[2 * (ng + 1) * 8: 2 * (ng + 1) * 8 + 4 * (npc + npp)].view(np.uint32)
+            return off[: ng + 1].copy(), ids[:npc].copy(), off[ng + 1:].copy(), ids[npc:].copy()
+        else:
+            raise ValueError(what)
+        self._check(self.L.bh_export(self.h, EXPORT[what], out.ctypes.data_as(C.c_void_p), _stream()))
+        return out
+
+    def export_groups(self):
+        ng = self.query()["n_groups"]
+        box = np.zeros((ng, 6), np.int32)
+        cen = np.zeros((ng, 3))
+        self._check(self.L.bh_export_groups(self.h, box.ctypes.data_as(C.c_void_p),
+                                            cen.ctypes.data_as(C.c_void_p), _stream()))
+        return box, cen
+
+    def stage_times(self):
+        ms = (C.c_double * 8)()
+        self._check(self.L.bh_stage_times(self.h, ms))
+        return dict(zip(STAGES, list(ms)))
+
+
+def to_device(system, device="cuda"):
+    """numpy System (paper_1907_02289_amd.inputs) -> dict of FP64 device tensors."""
+    import torch
+    return {k: torch.as_tensor(np.ascontiguousarray(getattr(system, k)), dtype=torch.float64, device=device)
+            for k in ("x", "y", "z", "vx", "vy", "vz", "m")}

@@ -1,0 +1,731 @@
+// bh_api.hip -- the C ABI of include/bh.h: context, device buffers with
+// capacity growth, the order of the stages of a timestep (Iwasawa et al.
+// 2019, Sec. 4.2: tree (3a), walk and lists (3d), interaction (3d),
+// integration (4), persistent lists reused over several steps), and export
+// of internal structures.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bh.h"
+#include "bh_internal.hpp"
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+enum StageEv { EV_KEYS = 0, EV_TREE, EV_MOM, EV_GROUPS, EV_WALK, EV_FORCE, EV_INTEG, EV_STEP, EV_N };
+
+}  // namespace
+
+struct bh_ctx {
+    bh_params P{};
+    std::string err;
+    int device = 0;
+    int n_cu = 256;
+
+    // host-side sizes of the current build
+    int n_sys = 0;
+    uint32_t n = 0;
+    std::vector<uint32_t> sys_off;
+    bool tree_valid = false, lists_valid = false;
+    uint32_t n_nodes = 0, n_groups = 0, max_level = 0;
+    uint64_t n_pc = 0, n_pp = 0, interactions = 0;
+    int n_grp_used = 64;
+
+    // capacities
+    uint32_t n_cap = 0, node_cap = 0, sys_cap = 0;
+    uint64_t pc_cap = 0, pp_cap = 0;
+    uint32_t walk_waves = 0, walk_front = 4096, walk_list = 8192;
+
+    // device buffers
+    DevBuf sys_off_b, sys_tab_b, acc_tab_b, box_b, box_part_b;
+    DevBuf pos_in, vel_in, idx_in, pos, vel, acc, idx;
+    DevBuf key, key_tmp, val, val_tmp, hist, scan_tmp;
+    DevBuf nd_prefix, nd_begin, nd_count, nd_first, nd_meta, nd_walk, nd_mom, nd_quad, tmp_a, tmp_b;
+    DevBuf gmark, grp, g_lo, g_hi, g_cen, g_pc_off, g_pc_len, g_pp_off, g_pp_len, g_cost, order;
+    DevBuf gkey_a, gkey_b, gval_a, gval_b;
+    DevBuf pc_pool, pp_pool, walk_scratch, counters;
+
+    // pinned host staging
+    DevCounters *h_cnt = nullptr;
+    SysPtr *h_systab = nullptr;
+    bhk::AccPtr *h_acctab = nullptr;
+    hipEvent_t tab_ev = nullptr;      // last copy out of the pinned tables
+    bool tab_ev_pending = false;
+
+    hipEvent_t ev0[EV_N] = {}, ev1[EV_N] = {};
+    bool ev_used[EV_N] = {};
+
+    DevState d{};
+};
+
+namespace {
+
+bh_status fail(bh_ctx *c, bh_status st, const std::string &msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+bh_status hipfail(bh_ctx *c, const char *what, hipError_t e) {
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    return fail(c, e == hipErrorOutOfMemory ? BH_ENOMEM : BH_EHIP, buf);
+}
+
+#define HIPCHK(c, x)                                    \
+    do {                                                \
+        hipError_t e_ = (x);                            \
+        if (e_ != hipSuccess) return hipfail(c, #x, e_); \
+    } while (0)
+
+#define STCHK(x)                      \
+    do {                              \
+        bh_status st_ = (x);          \
+        if (st_ != BH_OK) return st_; \
+    } while (0)
+
+hipError_t grow(DevBuf &b, size_t bytes) {
+    if (bytes <= b.bytes && b.p) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipSuccess) b.bytes = bytes;
+    return e;
+}
+
+void release(DevBuf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <typename T>
+T *P(DevBuf &b) {
+    return reinterpret_cast<T *>(b.p);
+}
+
+void refresh_state(bh_ctx *c) {
+    DevState &d = c->d;
+    d.n_sys = c->n_sys;
+    d.n = c->n;
+    d.sys_off = P<uint32_t>(c->sys_off_b);
+    d.sys_tab = P<SysPtr>(c->sys_tab_b);
+    d.box = P<double4>(c->box_b);
+    d.box_part = P<double>(c->box_part_b);
+    d.pos_in = P<double4>(c->pos_in);
+    d.vel_in = P<double4>(c->vel_in);
+    d.idx_in = P<uint32_t>(c->idx_in);
+    d.pos = P<double4>(c->pos);
+    d.vel = P<double4>(c->vel);
+    d.acc = P<double4>(c->acc);
+    d.idx = P<uint32_t>(c->idx);
+    d.key = P<uint64_t>(c->key);
+    d.key_tmp = P<uint64_t>(c->key_tmp);
+    d.val = P<uint32_t>(c->val);
+    d.val_tmp = P<uint32_t>(c->val_tmp);
+    d.hist = P<uint32_t>(c->hist);
+    d.scan_tmp = P<uint32_t>(c->scan_tmp);
+    d.node_cap = c->node_cap;
+    d.nd_prefix = P<uint64_t>(c->nd_prefix);
+    d.nd_begin = P<uint32_t>(c->nd_begin);
+    d.nd_count = P<uint32_t>(c->nd_count);
+    d.nd_first = P<uint32_t>(c->nd_first);
+    d.nd_meta = P<uint32_t>(c->nd_meta);
+    d.nd_walk = P<int4>(c->nd_walk);
+    d.nd_mom = P<double4>(c->nd_mom);
+    d.nd_quad = (c->P.criterion == BH_OPEN_LEARNED) ? P<double>(c->nd_quad) : nullptr;
+    d.tmp_a = P<uint32_t>(c->tmp_a);
+    d.tmp_b = P<uint32_t>(c->tmp_b);
+    d.gmark = P<uint32_t>(c->gmark);
+    d.grp = P<GroupInfo>(c->grp);
+    d.g_lo = P<int4>(c->g_lo);
+    d.g_hi = P<int4>(c->g_hi);
+    d.g_cen = P<double4>(c->g_cen);
+    d.g_pc_off = P<uint32_t>(c->g_pc_off);
+    d.g_pc_len = P<uint32_t>(c->g_pc_len);
+    d.g_pp_off = P<uint32_t>(c->g_pp_off);
+    d.g_pp_len = P<uint32_t>(c->g_pp_len);
+    d.g_cost = P<unsigned long long>(c->g_cost);
+    d.order = P<uint32_t>(c->order);
+    d.pc_pool = P<uint32_t>(c->pc_pool);
+    d.pp_pool = P<uint32_t>(c->pp_pool);
+    d.pc_cap = c->pc_cap;
+    d.pp_cap = c->pp_cap;
+    d.walk_scratch = P<uint32_t>(c->walk_scratch);
+    d.walk_front_cap = c->walk_front;
+    d.walk_list_cap = c->walk_list;
+    d.walk_waves = c->walk_waves;
+    d.cnt = P<DevCounters>(c->counters);
+    d.n_leaf = c->P.n_leaf;
+    d.n_grp = c->n_grp_used;
+    d.th2 = c->P.theta * c->P.theta;
+    d.eps2 = c->P.eps * c->P.eps;
+    d.G = c->P.G;
+    d.central_mass = c->P.central_mass;
+}
+
+bh_status check_params(const bh_params *p) {
+    if (!p) return BH_EINVAL;
+    if (!(p->theta >= 0.0) || !std::isfinite(p->theta)) return BH_EINVAL;
+    if (!(p->eps >= 0.0) || !std::isfinite(p->eps)) return BH_EINVAL;
+    if (!std::isfinite(p->G) || !std::isfinite(p->central_mass)) return BH_EINVAL;
+    if (p->n_leaf < 1 || p->n_leaf > 4096) return BH_EINVAL;
+    if (p->n_group > 65536) return BH_EINVAL;
+    if (p->precision != BH_FP64 && p->precision != BH_FP32_REL) return BH_EINVAL;
+    if (p->criterion != BH_OPEN_GEOMETRIC && p->criterion != BH_OPEN_LEARNED) return BH_EINVAL;
+    return BH_OK;
+}
+
+void ev_begin(bh_ctx *c, int k, hipStream_t s) {
+    (void)hipEventRecord(c->ev0[k], s);
+}
+void ev_end(bh_ctx *c, int k, hipStream_t s) {
+    (void)hipEventRecord(c->ev1[k], s);
+    c->ev_used[k] = true;
+}
+
+bh_status wait_tables(bh_ctx *c) {
+    if (c->tab_ev_pending) {
+        HIPCHK(c, hipEventSynchronize(c->tab_ev));
+        c->tab_ev_pending = false;
+    }
+    return BH_OK;
+}
+
+bh_status read_counters(bh_ctx *c, hipStream_t s) {
+    HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->counters.p, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return BH_OK;
+}
+
+bh_status ensure_systems(bh_ctx *c, int n_sys) {
+    if ((uint32_t)n_sys <= c->sys_cap && c->h_systab) return BH_OK;
+    uint32_t cap = std::max<uint32_t>(n_sys, 16);
+    STCHK(wait_tables(c));
+    HIPCHK(c, grow(c->sys_off_b, (cap + 1) * sizeof(uint32_t)));
+    HIPCHK(c, grow(c->sys_tab_b, cap * sizeof(SysPtr)));
+    HIPCHK(c, grow(c->acc_tab_b, cap * sizeof(bhk::AccPtr)));
+    HIPCHK(c, grow(c->box_b, cap * sizeof(double4)));
+    HIPCHK(c, grow(c->box_part_b, (size_t)cap * BOX_BLOCKS * 6 * sizeof(double)));
+    if (c->h_systab) (void)hipHostFree(c->h_systab);
+    if (c->h_acctab) (void)hipHostFree(c->h_acctab);
+    c->h_systab = nullptr;
+    c->h_acctab = nullptr;
+    HIPCHK(c, hipHostMalloc((void **)&c->h_systab, (cap + 1) * sizeof(SysPtr) + (cap + 1) * sizeof(uint32_t)));
+    HIPCHK(c, hipHostMalloc((void **)&c->h_acctab, cap * sizeof(bhk::AccPtr)));
+    c->sys_cap = cap;
+    return BH_OK;
+}
+
+bh_status ensure_particles(bh_ctx *c, uint32_t n) {
+    if (n <= c->n_cap && c->pos.p) return BH_OK;
+    uint32_t cap = std::max<uint32_t>(n, 1024);
+    size_t d4 = (size_t)cap * sizeof(double4), u4 = (size_t)cap * 4, u8 = (size_t)cap * 8;
+    HIPCHK(c, grow(c->pos_in, d4));
+    HIPCHK(c, grow(c->vel_in, d4));
+    HIPCHK(c, grow(c->idx_in, u4));
+    HIPCHK(c, grow(c->pos, d4));
+    HIPCHK(c, grow(c->vel, d4));
+    HIPCHK(c, grow(c->acc, d4));
+    HIPCHK(c, grow(c->idx, u4));
+    HIPCHK(c, grow(c->key, u8));
+    HIPCHK(c, grow(c->key_tmp, u8));
+    HIPCHK(c, grow(c->val, u4));
+    HIPCHK(c, grow(c->val_tmp, u4));
+    HIPCHK(c, grow(c->hist, bhk::radix_hist_words(cap) * 4));
+    HIPCHK(c, grow(c->scan_tmp, 4096 * 4));
+    HIPCHK(c, grow(c->gmark, u4));
+    HIPCHK(c, grow(c->grp, (size_t)cap * sizeof(GroupInfo)));
+    HIPCHK(c, grow(c->g_lo, (size_t)cap * sizeof(int4)));
+    HIPCHK(c, grow(c->g_hi, (size_t)cap * sizeof(int4)));
+    HIPCHK(c, grow(c->g_cen, d4));
+    HIPCHK(c, grow(c->g_pc_off, u4));
+    HIPCHK(c, grow(c->g_pc_len, u4));
+    HIPCHK(c, grow(c->g_pp_off, u4));
+    HIPCHK(c, grow(c->g_pp_len, u4));
+    HIPCHK(c, grow(c->g_cost, u8));
+    HIPCHK(c, grow(c->order, u4));
+    HIPCHK(c, grow(c->gkey_a, u8));
+    HIPCHK(c, grow(c->gkey_b, u8));
+    HIPCHK(c, grow(c->gval_a, u4));
+    HIPCHK(c, grow(c->gval_b, u4));
+    c->n_cap = cap;
+    return BH_OK;
+}
+
+bh_status ensure_nodes(bh_ctx *c, uint32_t cap) {
+    if (cap <= c->node_cap && c->nd_prefix.p) return BH_OK;
+    cap = std::max<uint32_t>(cap, 1024);
+    HIPCHK(c, grow(c->nd_prefix, (size_t)cap * 8));
+    HIPCHK(c, grow(c->nd_begin, (size_t)cap * 4));
+    HIPCHK(c, grow(c->nd_count, (size_t)cap * 4));
+    HIPCHK(c, grow(c->nd_first, (size_t)cap * 4));
+    HIPCHK(c, grow(c->nd_meta, (size_t)cap * 4));
+    HIPCHK(c, grow(c->nd_walk, (size_t)cap * sizeof(int4)));
+    HIPCHK(c, grow(c->nd_mom, (size_t)cap * sizeof(double4)));
+    if (c->P.criterion == BH_OPEN_LEARNED) HIPCHK(c, grow(c->nd_quad, (size_t)cap * 6 * sizeof(double)));
+    HIPCHK(c, grow(c->tmp_a, (size_t)cap * 4));
+    HIPCHK(c, grow(c->tmp_b, (size_t)cap * 4));
+    c->node_cap = cap;
+    return BH_OK;
+}
+
+bh_status ensure_walk(bh_ctx *c) {
+    size_t words = (size_t)c->walk_waves * (2 * (size_t)c->walk_front + 2 * (size_t)c->walk_list);
+    HIPCHK(c, grow(c->walk_scratch, words * 4));
+    return BH_OK;
+}
+
+bh_status ensure_pools(bh_ctx *c, uint64_t pc, uint64_t pp) {
+    if (pc > c->pc_cap || !c->pc_pool.p) {
+        HIPCHK(c, grow(c->pc_pool, std::max<uint64_t>(pc, 1024) * 4));
+        c->pc_cap = std::max<uint64_t>(pc, 1024);
+    }
+    if (pp > c->pp_cap || !c->pp_pool.p) {
+        HIPCHK(c, grow(c->pp_pool, std::max<uint64_t>(pp, 1024) * 4));
+        c->pp_cap = std::max<uint64_t>(pp, 1024);
+    }
+    return BH_OK;
+}
+
+// Stage (3a): everything from the input particles to groups.  from_caller:
+// load the caller's arrays; otherwise rebuild from the current sorted state.
+bh_status rebuild(bh_ctx *c, hipStream_t s, bool from_caller) {
+    if (!from_caller) {
+        std::swap(c->pos_in, c->pos);
+        std::swap(c->vel_in, c->vel);
+        std::swap(c->idx_in, c->idx);
+    }
+    refresh_state(c);
+    ev_begin(c, EV_KEYS, s);
+    bhk::reset_flags(c->d, s);
+    if (from_caller) bhk::load_systems(c->d, s);
+    bhk::root_box_keys(c->d, s);
+    bhk::permute(c->d, s);
+    ev_end(c, EV_KEYS, s);
+    for (;;) {
+        ev_begin(c, EV_TREE, s);
+        bhk::build_octree(c->d, s);
+        ev_end(c, EV_TREE, s);
+        STCHK(read_counters(c, s));
+        if (c->h_cnt->flags[FLAG_NONFINITE]) {
+            c->tree_valid = c->lists_valid = false;
+            return fail(c, BH_EINVAL, "non-finite particle coordinate");
+        }
+        if (c->h_cnt->flags[FLAG_NODE_OVF]) {
+            STCHK(ensure_nodes(c, c->node_cap * 2));
+            refresh_state(c);
+            continue;
+        }
+        break;
+    }
+    c->n_nodes = c->h_cnt->lvl_off[BH_NLEVELS];
+    c->max_level = c->h_cnt->max_level;
+    ev_begin(c, EV_MOM, s);
+    bhk::moments(c->d, s);
+    ev_end(c, EV_MOM, s);
+    ev_begin(c, EV_GROUPS, s);
+    bhk::make_groups(c->d, s);
+    ev_end(c, EV_GROUPS, s);
+    STCHK(read_counters(c, s));
+    c->n_groups = c->h_cnt->n_groups;
+    c->tree_valid = true;
+    c->lists_valid = false;
+    return BH_OK;
+}
+
+bh_status make_lists(bh_ctx *c, hipStream_t s) {
+    if (!c->tree_valid) return fail(c, BH_ESTATE, "bh_make_lists: no tree (call bh_build_tree first)");
+    for (int attempt = 0;; ++attempt) {
+        refresh_state(c);
+        ev_begin(c, EV_WALK, s);
+        bhk::walk(c->d, s);
+        ev_end(c, EV_WALK, s);
+        STCHK(read_counters(c, s));
+        const DevCounters &h = *c->h_cnt;
+        if (h.flags[FLAG_WALK_OVF]) {
+            if (attempt > 40) return fail(c, BH_ECAPACITY, "walk scratch cannot grow further");
+            if (h.walk_need_front >= c->walk_front) c->walk_front = std::max(2 * c->walk_front, 2 * h.walk_need_front);
+            if (h.walk_need_list >= c->walk_list) c->walk_list = std::max(2 * c->walk_list, 2 * h.walk_need_list);
+            // the frontier that overflowed may hide a longer list: grow both
+            c->walk_front = std::max(c->walk_front, c->walk_list);
+            c->walk_list = std::max(c->walk_list, c->walk_front);
+            STCHK(ensure_walk(c));
+            continue;
+        }
+        if (h.flags[FLAG_POOL_OVF]) {
+            STCHK(ensure_pools(c, h.pc_used + h.pc_used / 4 + 1024, h.pp_used + h.pp_used / 4 + 1024));
+            continue;
+        }
+        c->n_pc = h.pc_used;
+        c->n_pp = h.pp_used;
+        c->interactions = h.interactions;
+        break;
+    }
+    bhk::order_groups(c->d, c->n_groups, P<uint64_t>(c->gkey_a), P<uint32_t>(c->gval_a), P<uint64_t>(c->gkey_b),
+                      P<uint32_t>(c->gval_b), s);
+    c->lists_valid = true;
+    return BH_OK;
+}
+
+int force_blocks(const bh_ctx *c) { return c->n_cu * 8; }
+
+bh_status run_forces(bh_ctx *c, hipStream_t s, bool pot) {
+    ev_begin(c, EV_FORCE, s);
+    bhk::forces(c->d, c->n_groups, c->P.precision == BH_FP32_REL, pot, force_blocks(c), s);
+    ev_end(c, EV_FORCE, s);
+    return BH_OK;
+}
+
+bh_status set_systems(bh_ctx *c, const bh_system *sys, int32_t n_sys, hipStream_t s) {
+    if (!sys || n_sys < 1) return fail(c, BH_EINVAL, "need at least one system");
+    if (n_sys > 65535) return fail(c, BH_EINVAL, "too many systems (limit 65535)");
+    uint64_t total = 0;
+    for (int k = 0; k < n_sys; ++k) {
+        if (sys[k].n < 1) return fail(c, BH_EINVAL, "empty system");
+        if (!sys[k].x || !sys[k].y || !sys[k].z || !sys[k].m) return fail(c, BH_EINVAL, "null particle array");
+        total += (uint64_t)sys[k].n;
+    }
+    if (total >= (1ull << 31)) return fail(c, BH_EINVAL, "too many particles (limit 2^31 - 1)");
+    STCHK(ensure_systems(c, n_sys));
+    STCHK(wait_tables(c));
+    c->n_sys = n_sys;
+    c->n = (uint32_t)total;
+    c->sys_off.assign(n_sys + 1, 0);
+    for (int k = 0; k < n_sys; ++k) {
+        c->sys_off[k + 1] = c->sys_off[k] + (uint32_t)sys[k].n;
+        SysPtr &t = c->h_systab[k];
+        t.x = sys[k].x;
+        t.y = sys[k].y;
+        t.z = sys[k].z;
+        t.vx = sys[k].vx;
+        t.vy = sys[k].vy;
+        t.vz = sys[k].vz;
+        t.m = sys[k].m;
+        t.n = sys[k].n;
+    }
+    uint32_t *h_off = reinterpret_cast<uint32_t *>(c->h_systab + c->sys_cap + 1);
+    std::copy(c->sys_off.begin(), c->sys_off.end(), h_off);
+    HIPCHK(c, hipMemcpyAsync(c->sys_tab_b.p, c->h_systab, n_sys * sizeof(SysPtr), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->sys_off_b.p, h_off, (n_sys + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipEventRecord(c->tab_ev, s));
+    c->tab_ev_pending = true;
+    STCHK(ensure_particles(c, c->n));
+    if (c->node_cap < c->n + (uint32_t)n_sys) STCHK(ensure_nodes(c, c->n + n_sys + 1024));
+    if (!c->pc_pool.p) STCHK(ensure_pools(c, (uint64_t)c->n * 8 + 65536, (uint64_t)c->n * 2 + 65536));
+    return BH_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+bh_status bh_create(bh_ctx **out, const bh_params *p) {
+    if (!out) return BH_EINVAL;
+    *out = nullptr;
+    if (check_params(p) != BH_OK) return BH_EINVAL;
+    bh_ctx *c = new (std::nothrow) bh_ctx();
+    if (!c) return BH_ENOMEM;
+    c->P = *p;
+    c->n_grp_used = p->n_group > 0 ? p->n_group : 64;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return BH_EHIP;
+    }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
+        c->n_cu = ncu;
+    c->walk_waves = (uint32_t)c->n_cu * 16;
+    bool ok = hipHostMalloc((void **)&c->h_cnt, sizeof(DevCounters)) == hipSuccess &&
+              hipEventCreateWithFlags(&c->tab_ev, hipEventDisableTiming) == hipSuccess &&
+              grow(c->counters, sizeof(DevCounters)) == hipSuccess;
+    for (int k = 0; ok && k < EV_N; ++k)
+        ok = hipEventCreate(&c->ev0[k]) == hipSuccess && hipEventCreate(&c->ev1[k]) == hipSuccess;
+    if (!ok || ensure_walk(c) != BH_OK) {
+        bh_destroy(c);
+        return BH_ENOMEM;
+    }
+    (void)hipMemset(c->counters.p, 0, sizeof(DevCounters));
+    *out = c;
+    return BH_OK;
+}
+
+bh_status bh_destroy(bh_ctx *c) {
+    if (!c) return BH_EINVAL;
+    (void)hipDeviceSynchronize();
+    DevBuf *all[] = {&c->sys_off_b, &c->sys_tab_b, &c->acc_tab_b, &c->box_b, &c->box_part_b, &c->pos_in,
+                     &c->vel_in, &c->idx_in, &c->pos, &c->vel, &c->acc, &c->idx, &c->key, &c->key_tmp,
+                     &c->val, &c->val_tmp, &c->hist, &c->scan_tmp, &c->nd_prefix, &c->nd_begin, &c->nd_count,
+                     &c->nd_first, &c->nd_meta, &c->nd_walk, &c->nd_mom, &c->nd_quad, &c->tmp_a, &c->tmp_b,
+                     &c->gmark, &c->grp, &c->g_lo, &c->g_hi, &c->g_cen, &c->g_pc_off, &c->g_pc_len,
+                     &c->g_pp_off, &c->g_pp_len, &c->g_cost, &c->order, &c->gkey_a, &c->gkey_b, &c->gval_a,
+                     &c->gval_b, &c->pc_pool, &c->pp_pool, &c->walk_scratch, &c->counters};
+    for (DevBuf *b : all) release(*b);
+    if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+    if (c->h_systab) (void)hipHostFree(c->h_systab);
+    if (c->h_acctab) (void)hipHostFree(c->h_acctab);
+    if (c->tab_ev) (void)hipEventDestroy(c->tab_ev);
+    for (int k = 0; k < EV_N; ++k) {
+        if (c->ev0[k]) (void)hipEventDestroy(c->ev0[k]);
+        if (c->ev1[k]) (void)hipEventDestroy(c->ev1[k]);
+    }
+    delete c;
+    return BH_OK;
+}
+
+bh_status bh_set_params(bh_ctx *c, const bh_params *p) {
+    if (!c) return BH_EINVAL;
+    if (check_params(p) != BH_OK) return fail(c, BH_EINVAL, "invalid parameters");
+    int ng = p->n_group > 0 ? p->n_group : 64;
+    if (ng != c->n_grp_used || p->n_leaf != c->P.n_leaf || p->criterion != c->P.criterion) c->tree_valid = false;
+    c->P = *p;
+    c->n_grp_used = ng;
+    c->lists_valid = false;
+    if (c->P.criterion == BH_OPEN_LEARNED && c->node_cap) STCHK(ensure_nodes(c, c->node_cap + 1));
+    return BH_OK;
+}
+
+bh_status bh_build_tree(bh_ctx *c, const bh_system *sys, int32_t n_sys, void *stream) {
+    if (!c) return BH_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    c->tree_valid = c->lists_valid = false;
+    STCHK(set_systems(c, sys, n_sys, s));
+    return rebuild(c, s, true);
+}
+
+bh_status bh_make_lists(bh_ctx *c, void *stream) {
+    if (!c) return BH_EINVAL;
+    return make_lists(c, (hipStream_t)stream);
+}
+
+bh_status bh_forces(bh_ctx *c, const bh_accel *out, void *stream) {
+    if (!c) return BH_EINVAL;
+    if (!c->lists_valid) return fail(c, BH_ESTATE, "bh_forces: no interaction lists (call bh_make_lists)");
+    hipStream_t s = (hipStream_t)stream;
+    bool pot = false;
+    if (out)
+        for (int k = 0; k < c->n_sys; ++k) {
+            if (!out[k].ax || !out[k].ay || !out[k].az) return fail(c, BH_EINVAL, "null acceleration array");
+            pot |= out[k].pot != nullptr;
+        }
+    refresh_state(c);
+    STCHK(run_forces(c, s, pot || !out));
+    if (out) {
+        STCHK(wait_tables(c));
+        for (int k = 0; k < c->n_sys; ++k)
+            c->h_acctab[k] = bhk::AccPtr{out[k].ax, out[k].ay, out[k].az, out[k].pot};
+        HIPCHK(c, hipMemcpyAsync(c->acc_tab_b.p, c->h_acctab, c->n_sys * sizeof(bhk::AccPtr),
+                                 hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipEventRecord(c->tab_ev, s));
+        c->tab_ev_pending = true;
+        bhk::scatter_acc(c->d, P<bhk::AccPtr>(c->acc_tab_b), s);
+    }
+    HIPCHK(c, hipGetLastError());
+    return BH_OK;
+}
+
+bh_status bh_step(bh_ctx *c, const bh_system *sys, int32_t n_sys, double dt, int32_t n_steps,
+                  int32_t rebuild_every, void *stream) {
+    if (!c) return BH_EINVAL;
+    if (!std::isfinite(dt) || n_steps < 0 || rebuild_every < 1) return fail(c, BH_EINVAL, "bad step arguments");
+    for (int k = 0; sys && k < n_sys; ++k)
+        if (!sys[k].vx || !sys[k].vy || !sys[k].vz) return fail(c, BH_EINVAL, "bh_step needs velocities");
+    hipStream_t s = (hipStream_t)stream;
+    ev_begin(c, EV_STEP, s);
+    c->tree_valid = c->lists_valid = false;
+    STCHK(set_systems(c, sys, n_sys, s));
+    STCHK(rebuild(c, s, true));
+    STCHK(make_lists(c, s));
+    refresh_state(c);
+    STCHK(run_forces(c, s, false));
+    const double h = 0.5 * dt;
+    for (int k = 0; k < n_steps; ++k) {
+        ev_begin(c, EV_INTEG, s);
+        bhk::kick_drift(c->d, h, dt, s);
+        ev_end(c, EV_INTEG, s);
+        if ((k + 1) % rebuild_every == 0) {
+            STCHK(rebuild(c, s, false));
+            STCHK(make_lists(c, s));
+        } else {
+            ev_begin(c, EV_MOM, s);
+            bhk::moments(c->d, s);
+            ev_end(c, EV_MOM, s);
+        }
+        refresh_state(c);
+        STCHK(run_forces(c, s, false));
+        bhk::kick(c->d, h, s);
+    }
+    bhk::scatter_state(c->d, s);
+    ev_end(c, EV_STEP, s);
+    HIPCHK(c, hipGetLastError());
+    return BH_OK;
+}
+
+bh_status bh_query(const bh_ctx *c, bh_sizes *o) {
+    if (!c || !o) return BH_EINVAL;
+    o->n_particles = c->n;
+    o->n_systems = c->n_sys;
+    o->max_level = (int32_t)c->max_level;
+    o->n_nodes = c->tree_valid ? c->n_nodes : 0;
+    o->n_groups = c->tree_valid ? c->n_groups : 0;
+    o->n_pc = c->lists_valid ? (int64_t)c->n_pc : 0;
+    o->n_pp = c->lists_valid ? (int64_t)c->n_pp : 0;
+    o->interactions = c->lists_valid ? (int64_t)c->interactions : 0;
+    o->n_group_used = c->n_grp_used;
+    o->lists_valid = c->lists_valid ? 1 : 0;
+    return BH_OK;
+}
+
+bh_status bh_export(bh_ctx *c, int32_t what, void *dst, void *stream) {
+    if (!c || !dst) return BH_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipStreamSynchronize(s));
+    const size_t n = c->n, nn = c->n_nodes, ng = c->n_groups;
+    switch (what) {
+    case BH_EXPORT_KEYS:
+        if (!c->tree_valid) return fail(c, BH_ESTATE, "no tree");
+        HIPCHK(c, hipMemcpy(dst, c->key.p, n * 8, hipMemcpyDeviceToHost));
+        return BH_OK;
+    case BH_EXPORT_PERM: {
+        if (!c->tree_valid) return fail(c, BH_ESTATE, "no tree");
+        uint32_t *o = (uint32_t *)dst;
+        HIPCHK(c, hipMemcpy(o, c->idx.p, n * 4, hipMemcpyDeviceToHost));
+        for (size_t j = 0; j < n; ++j) {
+            auto it = std::upper_bound(c->sys_off.begin(), c->sys_off.end(), o[j]);
+            o[j] -= *(it - 1);
+        }
+        return BH_OK;
+    }
+    case BH_EXPORT_NODES: {
+        if (!c->tree_valid) return fail(c, BH_ESTATE, "no tree");
+        std::vector<uint64_t> pf(nn);
+        std::vector<uint32_t> b(nn), cn(nn), f(nn), m(nn);
+        HIPCHK(c, hipMemcpy(pf.data(), c->nd_prefix.p, nn * 8, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(b.data(), c->nd_begin.p, nn * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(cn.data(), c->nd_count.p, nn * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(f.data(), c->nd_first.p, nn * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(m.data(), c->nd_meta.p, nn * 4, hipMemcpyDeviceToHost));
+        int64_t *o = (int64_t *)dst;
+        for (size_t v = 0; v < nn; ++v) {
+            o[8 * v + 0] = meta_level(m[v]);
+            o[8 * v + 1] = meta_sys(m[v]);
+            o[8 * v + 2] = (int64_t)pf[v];
+            o[8 * v + 3] = b[v];
+            o[8 * v + 4] = cn[v];
+            o[8 * v + 5] = f[v];
+            o[8 * v + 6] = meta_nch(m[v]);
+            o[8 * v + 7] = meta_group(m[v]);
+        }
+        return BH_OK;
+    }
+    case BH_EXPORT_MOMENTS:
+        if (!c->tree_valid) return fail(c, BH_ESTATE, "no tree");
+        HIPCHK(c, hipMemcpy(dst, c->nd_mom.p, nn * sizeof(double4), hipMemcpyDeviceToHost));
+        return BH_OK;
+    case BH_EXPORT_GROUPS: {
+        if (!c->tree_valid) return fail(c, BH_ESTATE, "no tree");
+        std::vector<GroupInfo> g(ng);
+        HIPCHK(c, hipMemcpy(g.data(), c->grp.p, ng * sizeof(GroupInfo), hipMemcpyDeviceToHost));
+        int64_t *o = (int64_t *)dst;
+        for (size_t k = 0; k < ng; ++k) {
+            o[4 * k + 0] = g[k].node;
+            o[4 * k + 1] = g[k].begin;
+            o[4 * k + 2] = g[k].count;
+            o[4 * k + 3] = g[k].sys;
+        }
+        return BH_OK;
+    }
+    case BH_EXPORT_LISTS: {
+        if (!c->lists_valid) return fail(c, BH_ESTATE, "no lists");
+        std::vector<uint32_t> po(ng), pl(ng), qo(ng), ql(ng);
+        std::vector<uint32_t> pcp(c->n_pc), ppp(c->n_pp);
+        HIPCHK(c, hipMemcpy(po.data(), c->g_pc_off.p, ng * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(pl.data(), c->g_pc_len.p, ng * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(qo.data(), c->g_pp_off.p, ng * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(ql.data(), c->g_pp_len.p, ng * 4, hipMemcpyDeviceToHost));
+        if (c->n_pc) HIPCHK(c, hipMemcpy(pcp.data(), c->pc_pool.p, c->n_pc * 4, hipMemcpyDeviceToHost));
+        if (c->n_pp) HIPCHK(c, hipMemcpy(ppp.data(), c->pp_pool.p, c->n_pp * 4, hipMemcpyDeviceToHost));
+        int64_t *pc_off = (int64_t *)dst;
+        int64_t *pp_off = pc_off + ng + 1;
+        uint32_t *pc = (uint32_t *)(pp_off + ng + 1);
+        uint32_t *pp = pc + c->n_pc;
+        pc_off[0] = pp_off[0] = 0;
+        for (size_t k = 0; k < ng; ++k) {
+            std::copy(pcp.begin() + po[k], pcp.begin() + po[k] + pl[k], pc + pc_off[k]);
+            std::copy(ppp.begin() + qo[k], ppp.begin() + qo[k] + ql[k], pp + pp_off[k]);
+            pc_off[k + 1] = pc_off[k] + pl[k];
+            pp_off[k + 1] = pp_off[k] + ql[k];
+        }
+        return BH_OK;
+    }
+    case BH_EXPORT_ACC_SORTED:
+        HIPCHK(c, hipMemcpy(dst, c->acc.p, n * sizeof(double4), hipMemcpyDeviceToHost));
+        return BH_OK;
+    case BH_EXPORT_SORTED_POS:
+        HIPCHK(c, hipMemcpy(dst, c->pos.p, n * sizeof(double4), hipMemcpyDeviceToHost));
+        return BH_OK;
+    default:
+        return fail(c, BH_EINVAL, "unknown export item");
+    }
+}
+
+bh_status bh_export_groups(bh_ctx *c, int32_t *box, double *centre, void *stream) {
+    if (!c) return BH_EINVAL;
+    if (!c->tree_valid) return fail(c, BH_ESTATE, "no tree");
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    const size_t ng = c->n_groups;
+    if (box) {
+        std::vector<int4> lo(ng), hi(ng);
+        HIPCHK(c, hipMemcpy(lo.data(), c->g_lo.p, ng * sizeof(int4), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(hi.data(), c->g_hi.p, ng * sizeof(int4), hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < ng; ++k) {
+            int32_t *o = box + 6 * k;
+            o[0] = lo[k].x; o[1] = lo[k].y; o[2] = lo[k].z;
+            o[3] = hi[k].x; o[4] = hi[k].y; o[5] = hi[k].z;
+        }
+    }
+    if (centre) {
+        std::vector<double4> cc(ng);
+        HIPCHK(c, hipMemcpy(cc.data(), c->g_cen.p, ng * sizeof(double4), hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < ng; ++k) {
+            centre[3 * k] = cc[k].x;
+            centre[3 * k + 1] = cc[k].y;
+            centre[3 * k + 2] = cc[k].z;
+        }
+    }
+    return BH_OK;
+}
+
+bh_status bh_stage_times(bh_ctx *c, double *ms) {
+    if (!c || !ms) return BH_EINVAL;
+    for (int k = 0; k < EV_N; ++k) {
+        ms[k] = 0.0;
+        if (!c->ev_used[k]) continue;
+        HIPCHK(c, hipEventSynchronize(c->ev1[k]));
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->ev0[k], c->ev1[k]));
+        ms[k] = t;
+    }
+    return BH_OK;
+}
+
+const char *bh_last_error(const bh_ctx *c) {
+    return c ? c->err.c_str() : "null context";
+}
+
+}  // extern "C"

@@ -1,0 +1,238 @@
+// bh_force.hip -- the interaction double loop of Iwasawa et al. (2019)
+// Sec. 4.2 step (3d): for every group, every particle of the group against
+// every entry of the group's lists.  The pair term is the gravity branch of
+// Eq. (2) with Plummer softening,
+//     a_i += G m_j (x_j - x_i) / (|x_j - x_i|^2 + eps^2)^(3/2),
+// nodes acting as point masses at their centre of mass (Sec. 5.1).
+//
+// Precision (Sec. 4.7, shifted origin): in the FP32 variant the positions
+// of the group's particles and of every source are taken relative to the
+// group centre in FP64 and only then rounded to FP32; the pair terms and
+// their sums are FP32, the result is scaled by G and written in FP64.  The
+// FP64 variant is the same loop in double precision.
+//
+// Scheduling (Sec. 4.6): a persistent grid takes groups from an atomic
+// queue in order of decreasing interaction count, so the longest lists start
+// first and the tail is made of short ones.  All four waves of a workgroup
+// share one LDS tile of sources (the paper's cores sharing a cache on one
+// list): a group of up to 64 particles has its source range split four ways
+// over the waves, up to 128 two ways, larger groups one i-chunk per wave;
+// the per-wave partial sums are added in a fixed order, so results do not
+// depend on timing.
+#include "bh_internal.hpp"
+
+namespace {
+
+constexpr int FT = 256;      // threads per workgroup (4 waves)
+constexpr int TJ = 256;      // sources per LDS tile
+
+template <typename R> struct V4;
+template <> struct V4<float> { using T = float4; };
+template <> struct V4<double> { using T = double4; };
+
+template <typename R>
+__device__ __forceinline__ typename V4<R>::T mk4(R a, R b, R c, R e);
+template <>
+__device__ __forceinline__ float4 mk4<float>(float a, float b, float c, float e) { return make_float4(a, b, c, e); }
+template <>
+__device__ __forceinline__ double4 mk4<double>(double a, double b, double c, double e) {
+    return make_double4(a, b, c, e);
+}
+
+template <typename R>
+__device__ __forceinline__ R rsqrt_r(R x);
+template <>
+__device__ __forceinline__ float rsqrt_r<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <>
+__device__ __forceinline__ double rsqrt_r<double>(double x) { return 1.0 / sqrt(x); }
+
+template <typename R>
+__device__ __forceinline__ R fma_r(R a, R b, R c);
+template <>
+__device__ __forceinline__ float fma_r<float>(float a, float b, float c) { return fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double fma_r<double>(double a, double b, double c) { return fma(a, b, c); }
+
+// One pass of a wave over sources [j0, j1) of the LDS tile.
+template <typename R, bool POT, bool ZERO_EPS>
+__device__ __forceinline__ void interact(const typename V4<R>::T *tile, int j0, int j1, R xi, R yi, R zi, R eps2,
+                                         R &ax, R &ay, R &az, R &pot) {
+#pragma unroll 4
+    for (int j = j0; j < j1; ++j) {
+        const typename V4<R>::T s = tile[j];
+        const R dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+        const R r2 = fma_r<R>(dx, dx, fma_r<R>(dy, dy, fma_r<R>(dz, dz, eps2)));
+        R ri = rsqrt_r<R>(r2);
+        if (ZERO_EPS) ri = (r2 > (R)0) ? ri : (R)0;
+        const R mri = s.w * ri;
+        const R f = mri * (ri * ri);
+        ax = fma_r<R>(f, dx, ax);
+        ay = fma_r<R>(f, dy, ay);
+        az = fma_r<R>(f, dz, az);
+        if (POT) pot -= mri;
+    }
+}
+
+template <typename R, bool POT, bool ZERO_EPS>
+__global__ void __launch_bounds__(FT) k_force(DevState d, uint32_t ng) {
+    using T4 = typename V4<R>::T;
+    __shared__ T4 tile[TJ];
+    __shared__ uint32_t lbeg[TJ];
+    __shared__ uint32_t lscan[TJ + 1];
+    __shared__ R red[4][4][64];
+    __shared__ uint32_t s_item;
+    __shared__ uint32_t wsum[4];
+
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = __lane_id();
+    const R eps2 = (R)d.eps2;
+
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&d.cnt->work_counter2, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= ng) break;
+        const uint32_t g = d.order[item];
+        const GroupInfo gi = d.grp[g];
+        const double4 cen = d.g_cen[g];
+        const uint32_t pc0 = d.g_pc_off[g], npc = d.g_pc_len[g];
+        const uint32_t pp0 = d.g_pp_off[g], npp = d.g_pp_len[g];
+
+        for (uint32_t ib = 0; ib < gi.count; ib += FT) {
+            const uint32_t nb = min((uint32_t)FT, gi.count - ib);
+            const int n_ic = (int)((nb + 63) >> 6);
+            const int split = 4 / n_ic;
+            const int ichunk = w % n_ic;
+            const int jslice = w / n_ic;
+            const bool wave_on = jslice < split;
+            const uint32_t il = ichunk * 64 + lane;
+            const bool ion = wave_on && il < nb;
+            const uint32_t i = gi.begin + ib + il;
+            R xi = 0, yi = 0, zi = 0;
+            if (ion) {
+                const double4 p = d.pos[i];
+                xi = (R)(p.x - cen.x);
+                yi = (R)(p.y - cen.y);
+                zi = (R)(p.z - cen.z);
+            }
+            R ax = 0, ay = 0, az = 0, pot = 0;
+
+            // ---- node list: centre of mass and mass of each accepted node
+            for (uint32_t t0 = 0; t0 < npc; t0 += TJ) {
+                const uint32_t cntt = min((uint32_t)TJ, npc - t0);
+                if ((uint32_t)tid < cntt) {
+                    const double4 m = d.nd_mom[d.pc_pool[pc0 + t0 + tid]];
+                    tile[tid] = mk4<R>((R)(m.x - cen.x), (R)(m.y - cen.y), (R)(m.z - cen.z), (R)m.w);
+                }
+                __syncthreads();
+                if (wave_on) {
+                    const int j0 = (int)(cntt * jslice / split), j1 = (int)(cntt * (jslice + 1) / split);
+                    interact<R, POT, ZERO_EPS>(tile, j0, j1, xi, yi, zi, eps2, ax, ay, az, pot);
+                }
+                __syncthreads();
+            }
+
+            // ---- particle list: the particles of each listed leaf
+            for (uint32_t l0 = 0; l0 < npp; l0 += TJ) {
+                const uint32_t nl = min((uint32_t)TJ, npp - l0);
+                uint32_t lc = 0, lb = 0;
+                if ((uint32_t)tid < nl) {
+                    const uint32_t leaf = d.pp_pool[pp0 + l0 + tid];
+                    lb = d.nd_begin[leaf];
+                    lc = d.nd_count[leaf];
+                }
+                // exclusive scan of leaf sizes over the workgroup
+                const uint32_t inc = wave_incl_scan(lc);
+                if (lane == 63) wsum[w] = inc;
+                __syncthreads();
+                uint32_t off = 0, tot = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    off += (k < w) ? wsum[k] : 0u;
+                    tot += wsum[k];
+                }
+                lbeg[tid] = lb;
+                lscan[tid] = off + inc - lc;
+                __syncthreads();
+                for (uint32_t p0 = 0; p0 < tot; p0 += TJ) {
+                    const uint32_t cntt = min((uint32_t)TJ, tot - p0);
+                    if ((uint32_t)tid < cntt) {
+                        const uint32_t f = p0 + tid;
+                        uint32_t lo = 0, hi = nl - 1;          // last k with lscan[k] <= f
+                        while (lo < hi) {
+                            const uint32_t mid = (lo + hi + 1) >> 1;
+                            if (lscan[mid] <= f) lo = mid; else hi = mid - 1;
+                        }
+                        const double4 q = d.pos[lbeg[lo] + (f - lscan[lo])];
+                        tile[tid] = mk4<R>((R)(q.x - cen.x), (R)(q.y - cen.y), (R)(q.z - cen.z), (R)q.w);
+                    }
+                    __syncthreads();
+                    if (wave_on) {
+                        const int j0 = (int)(cntt * jslice / split), j1 = (int)(cntt * (jslice + 1) / split);
+                        interact<R, POT, ZERO_EPS>(tile, j0, j1, xi, yi, zi, eps2, ax, ay, az, pot);
+                    }
+                    __syncthreads();
+                }
+            }
+
+            // ---- add the j-slices in a fixed order and write FP64 results
+            red[0][w][lane] = ax;
+            red[1][w][lane] = ay;
+            red[2][w][lane] = az;
+            red[3][w][lane] = pot;
+            __syncthreads();
+            if (ion && jslice == 0) {
+                R sx = 0, sy = 0, sz = 0, sp = 0;
+                for (int k = 0; k < split; ++k) {
+                    const int ww = k * n_ic + ichunk;
+                    sx += red[0][ww][lane];
+                    sy += red[1][ww][lane];
+                    sz += red[2][ww][lane];
+                    sp += red[3][ww][lane];
+                }
+                double gx = d.G * (double)sx, gy = d.G * (double)sy, gz = d.G * (double)sz;
+                if (d.central_mass != 0.0) {
+                    const double4 p = d.pos[i];
+                    const double r2 = p.x * p.x + p.y * p.y + p.z * p.z;
+                    const double r = sqrt(r2);
+                    const double f = -d.G * d.central_mass / (r2 * r);
+                    gx += f * p.x;
+                    gy += f * p.y;
+                    gz += f * p.z;
+                }
+                d.acc[i] = make_double4(gx, gy, gz, POT ? d.G * (double)sp : 0.0);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void k_force_reset(DevState d) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) d.cnt->work_counter2 = 0;
+}
+
+template <typename R, bool POT>
+void launch(const DevState &d, uint32_t ng, int blocks, hipStream_t s) {
+    if (d.eps2 == 0.0)
+        k_force<R, POT, true><<<blocks, FT, 0, s>>>(d, ng);
+    else
+        k_force<R, POT, false><<<blocks, FT, 0, s>>>(d, ng);
+}
+
+}  // namespace
+
+namespace bhk {
+
+void forces(const DevState &d, uint32_t n_groups, bool fp32, bool pot, int blocks, hipStream_t s) {
+    k_force_reset<<<1, 64, 0, s>>>(d);
+    if (n_groups == 0) return;
+    if (fp32) {
+        if (pot) launch<float, true>(d, n_groups, blocks, s); else launch<float, false>(d, n_groups, blocks, s);
+    } else {
+        if (pot) launch<double, true>(d, n_groups, blocks, s); else launch<double, false>(d, n_groups, blocks, s);
+    }
+}
+
+}  // namespace bhk

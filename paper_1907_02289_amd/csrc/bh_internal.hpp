@@ -1,0 +1,219 @@
+// bh_internal.hpp -- device helpers and host launchers shared by the HIP
+// translation units of the Barnes-Hut library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define BH_MAXLEVEL 21          // 21 bits per axis, 63-bit keys
+#define BH_NLEVELS 22           // levels 0..21
+#define BH_WAVE 64
+
+// ---------------------------------------------------------------- errors
+// Device-side flags, one word each, in a small array the host reads back.
+enum {
+    FLAG_NONFINITE = 0,         // a coordinate was NaN or Inf
+    FLAG_NODE_OVF = 1,          // node capacity exceeded
+    FLAG_WALK_OVF = 2,          // a walk frontier/list scratch overflowed
+    FLAG_POOL_OVF = 3,          // list pool capacity exceeded
+    FLAG_COUNT = 8
+};
+
+// Device counters written by kernels and read back by the host.
+struct DevCounters {
+    uint32_t flags[FLAG_COUNT];
+    uint32_t lvl_off[BH_NLEVELS + 2];   // node-id range of each level
+    uint32_t n_groups;
+    uint32_t max_level;
+    unsigned long long pc_used;         // list-pool fill (may exceed capacity: overflow)
+    unsigned long long pp_used;
+    unsigned long long interactions;
+    uint32_t walk_need_front;           // largest frontier seen
+    uint32_t walk_need_list;            // longest list seen
+    uint32_t work_counter;              // persistent-kernel work queue head
+    uint32_t work_counter2;
+    uint32_t pad[4];
+};
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    int l = __lane_id();
+    return (l == 0) ? 0ull : (~0ull >> (64 - l));
+}
+
+// inclusive prefix sum over the 64 lanes of a wave
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T u = __shfl_up(v, d, 64);
+        if (__lane_id() >= d) v += u;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        T u = __shfl_xor(v, d, 64);
+        v = u < v ? u : v;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        T u = __shfl_xor(v, d, 64);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+// Morton helpers: 21 bits per axis, x the most significant bit of each triple.
+__host__ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1fffffull;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__host__ __device__ __forceinline__ uint32_t compact3(uint64_t x) {
+    x &= 0x1249249249249249ull;
+    x = (x | (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x | (x >> 8)) & 0x1f0000ff0000ffull;
+    x = (x | (x >> 16)) & 0x1f00000000ffffull;
+    x = (x | (x >> 32)) & 0x1fffffull;
+    return (uint32_t)x;
+}
+
+// ---------------------------------------------------------------- device state
+// Caller pointers of one system, as a device-side table.
+struct SysPtr {
+    double *x, *y, *z, *vx, *vy, *vz;
+    const double *m;
+    int64_t n;
+};
+
+// Node meta word: level (5 bits) | n_child (4 bits) << 5 | is_group << 9 | system << 10
+__host__ __device__ __forceinline__ uint32_t meta_level(uint32_t m) { return m & 31u; }
+__host__ __device__ __forceinline__ uint32_t meta_nch(uint32_t m) { return (m >> 5) & 15u; }
+__host__ __device__ __forceinline__ uint32_t meta_group(uint32_t m) { return (m >> 9) & 1u; }
+__host__ __device__ __forceinline__ uint32_t meta_sys(uint32_t m) { return m >> 10; }
+__host__ __device__ __forceinline__ uint32_t make_meta(uint32_t lvl, uint32_t nch, uint32_t grp, uint32_t sys) {
+    return lvl | (nch << 5) | (grp << 9) | (sys << 10);
+}
+
+// Per-group record: node id, first particle, particle count, system.
+struct GroupInfo {
+    uint32_t node, begin, count, sys;
+};
+
+// Raw device pointers of a context, passed by value to the launchers.
+struct DevState {
+    // systems
+    int n_sys;
+    uint32_t n;                    // particles over all systems
+    const uint32_t *sys_off;       // [n_sys+1]
+    const SysPtr *sys_tab;         // [n_sys]
+    double4 *box;                  // [n_sys]: lo x, y, z, 2^21 / S
+    double *box_part;              // [n_sys][BOX_BLOCKS][6]
+    // particles: input order of the current build and sorted order
+    double4 *pos_in, *vel_in;
+    uint32_t *idx_in;
+    double4 *pos, *vel, *acc;      // sorted: (x,y,z,m), (vx,vy,vz,0), (ax,ay,az,pot)
+    uint32_t *idx;                 // sorted slot -> global caller index
+    uint64_t *key, *key_tmp;
+    uint32_t *val, *val_tmp, *hist, *scan_tmp;
+    // tree
+    uint32_t node_cap;
+    uint64_t *nd_prefix;
+    uint32_t *nd_begin, *nd_count, *nd_first, *nd_meta;
+    int4 *nd_walk;                 // corner x | level << 24, corner y | n_child << 24, corner z, first child
+    double4 *nd_mom;               // com x, y, z, mass
+    double *nd_quad;               // [node_cap][6] second moments (learned rule only), may be null
+    uint32_t *tmp_a, *tmp_b;       // [node_cap] level scratch
+    // groups
+    uint32_t *gmark;               // [n] particle marks, then group index
+    GroupInfo *grp;                // [n] (capacity: one per particle)
+    int4 *g_lo, *g_hi;             // grid box, half-open
+    double4 *g_cen;
+    // lists
+    uint32_t *g_pc_off, *g_pc_len, *g_pp_off, *g_pp_len;
+    unsigned long long *g_cost;    // interactions of the group
+    uint32_t *order;               // groups by descending cost
+    uint32_t *pc_pool, *pp_pool;
+    unsigned long long pc_cap, pp_cap;
+    uint32_t *walk_scratch;        // per walking wave: 2 frontiers + 2 lists
+    uint32_t walk_front_cap, walk_list_cap, walk_waves;
+    DevCounters *cnt;
+    // parameters
+    int n_leaf, n_grp;
+    double th2;                    // theta * theta
+    double eps2, G, central_mass;
+};
+
+constexpr int BOX_BLOCKS = 64;
+
+// ---------------------------------------------------------------- host launchers
+namespace bhk {
+
+// tree build (bh_tree.hip)
+void load_systems(const DevState &d, hipStream_t s);
+void root_box_keys(const DevState &d, hipStream_t s);
+void permute(const DevState &d, hipStream_t s);
+void build_octree(const DevState &d, hipStream_t s);
+void moments(const DevState &d, hipStream_t s);
+void make_groups(const DevState &d, hipStream_t s);
+void reset_flags(const DevState &d, hipStream_t s);
+
+// lists (bh_walk.hip)
+void walk(const DevState &d, hipStream_t s);
+void order_groups(const DevState &d, uint32_t n_groups, uint64_t *key_a, uint32_t *val_a, uint64_t *key_b,
+                  uint32_t *val_b, hipStream_t s);
+
+// forces (bh_force.hip): blocks = persistent workgroups
+void forces(const DevState &d, uint32_t n_groups, bool fp32, bool pot, int blocks, hipStream_t s);
+
+// integration and caller-order output (bh_integrate.hip)
+struct AccPtr {
+    double *ax, *ay, *az, *pot;
+};
+void kick_drift(const DevState &d, double h, double dt, hipStream_t s);
+void kick(const DevState &d, double h, hipStream_t s);
+void scatter_state(const DevState &d, hipStream_t s);
+void scatter_acc(const DevState &d, const AccPtr *tab, hipStream_t s);
+
+// exclusive scan of n uint32 (n from *n_dev when n_dev != nullptr, else n_host);
+// out may alias in.  *total (if non-null) receives the sum.  tmp: >= 1024 words.
+void scan_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint32_t n_host,
+              uint32_t *total, uint32_t *tmp, hipStream_t s);
+
+// fill n words with v (graph-safe replacement for hipMemsetAsync)
+void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+
+// Stable LSD radix sort of (key, val) pairs by key bits [lo_bit, hi_bit),
+// then (when sys_off != nullptr and n_sys > 1) by the system owning input
+// index val (sys_off: device array of n_sys+1 offsets), so the result is in
+// (system, key, input order).  Result in key_a/val_a.  Scratch: key_b/val_b
+// of n, hist of radix_hist_words(n).
+size_t radix_hist_words(uint32_t n);
+void radix_sort(uint64_t *key_a, uint32_t *val_a, uint64_t *key_b, uint32_t *val_b,
+                uint32_t n, int lo_bit, int hi_bit, uint32_t *hist, uint32_t *tmp, hipStream_t s,
+                const uint32_t *sys_off, int n_sys);
+
+}  // namespace bhk

@@ -1,0 +1,189 @@
+// bh_walk.hip -- interaction lists, Iwasawa et al. (2019) Sec. 4.2 step (3d):
+// the tree is traversed once per group of neighbouring particles (the group
+// variant of the walk), producing the list of tree nodes and the list of
+// particles (as leaves) that act on the group; the lists are kept and reused
+// over several steps (the persistent interaction list of Sec. 4.2).
+//
+// One wavefront walks one group.  The traversal is breadth first: the 64
+// lanes test 64 frontier nodes at a time and ballots / a wave prefix sum
+// compact the three outcomes (accepted node -> node list, rejected leaf ->
+// particle list, rejected internal node -> its children join the next
+// frontier).  Frontier order is ascending node id at every level, so both
+// lists come out in ascending node id without a sort.
+//
+// Opening test (the paper states none; reading): a node is accepted when it
+// lies outside the group's grid box and side < theta * distance from the
+// node's centre to the box, evaluated in doubled integer grid units with a
+// single FP64 multiply, so every device decides exactly alike.
+#include "bh_internal.hpp"
+
+namespace {
+
+constexpr int WALK_TPB = 256;
+
+__device__ __forceinline__ bool accept_cell(int4 glo, int4 ghi, int Lx, int Ly, int Lz, int level, double th2) {
+    const int64_t s = (int64_t)1 << (BH_MAXLEVEL - level);
+    const int64_t L[3] = {Lx, Ly, Lz};
+    const int64_t gl[3] = {glo.x, glo.y, glo.z}, gh[3] = {ghi.x, ghi.y, ghi.z};
+    bool disjoint = false;
+    int64_t d2 = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        disjoint |= (L[a] + s <= gl[a]) || (L[a] >= gh[a]);
+        int64_t C = 2 * L[a] + s;
+        int64_t da = 0;
+        da = (2 * gl[a] - C > da) ? 2 * gl[a] - C : da;
+        da = (C - 2 * gh[a] > da) ? C - 2 * gh[a] : da;
+        d2 += da * da;
+    }
+    const int64_t s2 = (2 * s) * (2 * s);
+    return disjoint && ((double)s2 < th2 * (double)d2);
+}
+
+__global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
+    const uint32_t wave = (blockIdx.x * WALK_TPB + threadIdx.x) >> 6;
+    if (wave >= d.walk_waves) return;
+    const int lane = __lane_id();
+    const uint64_t lt = lanemask_lt();
+    const uint32_t F = d.walk_front_cap, P = d.walk_list_cap;
+    uint32_t *fa = d.walk_scratch + (size_t)wave * (2 * (size_t)F + 2 * (size_t)P);
+    uint32_t *fb = fa + F;
+    uint32_t *pcb = fb + F;
+    uint32_t *ppb = pcb + P;
+    const uint32_t ng = d.cnt->n_groups;
+    const double th2 = d.th2;
+
+    for (;;) {
+        uint32_t g = 0;
+        if (lane == 0) g = atomicAdd(&d.cnt->work_counter, 1u);
+        g = __shfl(g, 0, 64);
+        if (g >= ng) break;
+        const GroupInfo gi = d.grp[g];
+        const int4 glo = d.g_lo[g], ghi = d.g_hi[g];
+        uint32_t *cur = fa, *nxt = fb;
+        if (lane == 0) cur[0] = gi.sys;          // root of the group's system
+        __threadfence_block();
+        uint32_t ncur = 1, npc = 0, npp = 0;
+        unsigned long long pp_particles = 0;
+        bool ovf = false;
+        while (ncur > 0 && !ovf) {
+            uint32_t nnext = 0;
+            for (uint32_t base = 0; base < ncur; base += 64) {
+                const uint32_t k = base + lane;
+                const bool valid = k < ncur;
+                const uint32_t v = valid ? cur[k] : 0u;
+                int4 wr = valid ? d.nd_walk[v] : make_int4(0, 0, 0, 0);
+                const int level = (int)((uint32_t)wr.x >> 24);
+                const int nch = (int)((uint32_t)wr.y >> 24);
+                const bool acc = valid && accept_cell(glo, ghi, wr.x & 0xffffff, wr.y & 0xffffff, wr.z, level, th2);
+                const bool is_pp = valid && !acc && nch == 0;
+                const uint32_t nopen = (valid && !acc && nch > 0) ? (uint32_t)nch : 0u;
+
+                const uint64_t mpc = __ballot(acc);
+                const uint64_t mpp = __ballot(is_pp);
+                const uint32_t opc = npc + (uint32_t)__popcll(mpc & lt);
+                const uint32_t opp = npp + (uint32_t)__popcll(mpp & lt);
+                if (acc && opc < P) pcb[opc] = v;
+                if (is_pp && opp < P) ppb[opp] = v;
+                unsigned long long cnt_pp = is_pp ? (unsigned long long)d.nd_count[v] : 0ull;
+                pp_particles += wave_sum(cnt_pp);
+                npc += (uint32_t)__popcll(mpc);
+                npp += (uint32_t)__popcll(mpp);
+
+                const uint32_t incl = wave_incl_scan(nopen);
+                const uint32_t tot = __shfl(incl, 63, 64);
+                const uint32_t o = nnext + incl - nopen;
+                for (uint32_t c = 0; c < nopen; ++c)
+                    if (o + c < F) nxt[o + c] = (uint32_t)wr.w + c;
+                nnext += tot;
+            }
+            if (nnext > F || npc > P || npp > P) ovf = true;
+            __threadfence_block();
+            uint32_t *t = cur; cur = nxt; nxt = t;
+            ncur = nnext;
+        }
+        if (ovf) {
+            if (lane == 0) {
+                atomicOr(&d.cnt->flags[FLAG_WALK_OVF], 1u);
+                atomicMax(&d.cnt->walk_need_front, ncur);
+                atomicMax(&d.cnt->walk_need_list, max(npc, npp));
+            }
+            d.g_pc_len[g] = 0;
+            d.g_pp_len[g] = 0;
+            d.g_cost[g] = 0;
+            continue;
+        }
+        unsigned long long at_pc = 0, at_pp = 0;
+        if (lane == 0) {
+            at_pc = atomicAdd(&d.cnt->pc_used, (unsigned long long)npc);
+            at_pp = atomicAdd(&d.cnt->pp_used, (unsigned long long)npp);
+        }
+        at_pc = __shfl(at_pc, 0, 64);
+        at_pp = __shfl(at_pp, 0, 64);
+        const bool fit = (at_pc + npc <= d.pc_cap) && (at_pp + npp <= d.pp_cap);
+        if (fit) {
+            for (uint32_t k = lane; k < npc; k += 64) d.pc_pool[at_pc + k] = pcb[k];
+            for (uint32_t k = lane; k < npp; k += 64) d.pp_pool[at_pp + k] = ppb[k];
+        } else if (lane == 0) {
+            atomicOr(&d.cnt->flags[FLAG_POOL_OVF], 1u);
+        }
+        const unsigned long long cost = (unsigned long long)gi.count * (pp_particles + npc);
+        if (lane == 0) {
+            d.g_pc_off[g] = fit ? (uint32_t)at_pc : 0u;
+            d.g_pc_len[g] = fit ? npc : 0u;
+            d.g_pp_off[g] = fit ? (uint32_t)at_pp : 0u;
+            d.g_pp_len[g] = fit ? npp : 0u;
+            d.g_cost[g] = cost;
+            atomicAdd(&d.cnt->interactions, cost);
+        }
+        __threadfence_block();
+    }
+}
+
+__global__ void k_walk_reset(DevState d) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        d.cnt->work_counter = 0;
+        d.cnt->pc_used = 0;
+        d.cnt->pp_used = 0;
+        d.cnt->interactions = 0;
+        d.cnt->walk_need_front = 0;
+        d.cnt->walk_need_list = 0;
+        d.cnt->flags[FLAG_WALK_OVF] = 0;
+        d.cnt->flags[FLAG_POOL_OVF] = 0;
+    }
+}
+
+// Work order for the force kernel: groups by descending interaction count
+// (the list-length ordering of the paper's load balance, Sec. 4.6).
+__global__ void k_order_keys(DevState d, uint64_t *key, uint32_t *val) {
+    const uint32_t ng = d.cnt->n_groups;
+    uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += stride) {
+        unsigned long long c = d.g_cost[g];
+        const unsigned long long cap = (1ull << 40) - 1;
+        key[g] = cap - (c < cap ? c : cap);
+        val[g] = g;
+    }
+}
+
+}  // namespace
+
+namespace bhk {
+
+void walk(const DevState &d, hipStream_t s) {
+    k_walk_reset<<<1, 64, 0, s>>>(d);
+    unsigned blocks = (d.walk_waves * 64 + WALK_TPB - 1) / WALK_TPB;
+    k_walk<<<blocks, WALK_TPB, 0, s>>>(d);
+}
+
+void order_groups(const DevState &d, uint32_t n_groups, uint64_t *key_a, uint32_t *val_a, uint64_t *key_b,
+                  uint32_t *val_b, hipStream_t s) {
+    if (n_groups == 0) return;
+    unsigned blocks = (n_groups + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    k_order_keys<<<blocks, 256, 0, s>>>(d, key_a, val_a);
+    radix_sort(key_a, val_a, key_b, val_b, n_groups, 0, 40, d.hist, d.scan_tmp, s, nullptr, 0);
+    hipMemcpyAsync(d.order, val_a, (size_t)n_groups * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+}
+
+}  // namespace bhk

@@ -1,0 +1,215 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars: keys, permutation, tree, groups, group boxes and lists bit-exact;
+moments within the FP64 summation bound; FP64 forces per particle within 1e-12 of the
+sum of the magnitudes of the terms; FP32-relative forces with median
+relative error <= 1e-5 (p99 and max reported) against the oracle evaluating
+the same lists in FP64.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_02289_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _ctx(theta, eps, n_leaf=8, n_grp=64, precision=0, central_mass=0.0):
+    from paper_1907_02289_amd import bh
+    return bh.Context(theta=theta, eps=eps, n_leaf=n_leaf, n_group=n_grp, precision=precision,
+                      central_mass=central_mass)
+
+
+def _gpu_build(torch, systems, theta, eps, n_leaf=8, n_grp=64, precision=0, central_mass=0.0):
+    from paper_1907_02289_amd import bh
+    ctx = _ctx(theta, eps, n_leaf, n_grp, precision, central_mass)
+    dev = [bh.to_device(s) for s in systems]
+    ctx.build_tree(dev)
+    ctx.make_lists()
+    return ctx, dev
+
+
+def _compare_structures(ctx, st, n):
+    keys = ctx.export("keys")
+    np.testing.assert_array_equal(keys, st.skey)
+    np.testing.assert_array_equal(ctx.export("perm"), st.perm)
+    nodes = ctx.export("nodes")
+    t = st.tree
+    assert nodes.shape[0] == t["begin"].size
+    np.testing.assert_array_equal(nodes[:, 0], t["level"])
+    np.testing.assert_array_equal(nodes[:, 2].astype(np.uint64), t["prefix"])
+    np.testing.assert_array_equal(nodes[:, 3], t["begin"])
+    np.testing.assert_array_equal(nodes[:, 4], t["count"])
+    np.testing.assert_array_equal(nodes[:, 6], t["n_child"])
+    inner = t["n_child"] > 0
+    np.testing.assert_array_equal(nodes[inner, 5], t["first_child"][inner])
+    mom = ctx.export("moments")
+    # The oracle sums each node's particles one after another, the GPU sums
+    # children level by level: both are FP64 sums of `count` positive terms,
+    # each within (count - 1) u of the exact value (u = 2^-53), so they agree
+    # to (2 count + 64) u relative; the centre of mass to that times the
+    # largest |coordinate| in play.
+    u = 2.0 ** -53
+    cnt = t["count"].astype(np.float64)
+    tol = np.maximum(1e-14, (2 * cnt + 64) * u)
+    M = st.mom["M"]
+    assert np.all(np.abs(mom[:, 3] - M) <= tol * M)
+    pos = ctx.export("sorted_pos")
+    scale = np.abs(pos[:, :3]).max() + 1e-300
+    for k, key in enumerate(("cx", "cy", "cz")):
+        assert np.all(np.abs(mom[:, k] - st.mom[key]) <= 4 * tol * scale)
+    groups = ctx.export("groups")
+    np.testing.assert_array_equal(groups[:, 0], st.gnode)
+    box, cen = ctx.export_groups()
+    np.testing.assert_array_equal(box, st.gbox)
+    np.testing.assert_array_equal(cen, st.gcen)
+    pc_off, pc, pp_off, pp = ctx.export("lists")
+    np.testing.assert_array_equal(pc_off, st.pc_off)
+    np.testing.assert_array_equal(pp_off, st.pp_off)
+    np.testing.assert_array_equal(pc, st.pc)
+    np.testing.assert_array_equal(pp, st.pp)
+    assert ctx.query()["interactions"] == st.interactions()
+
+
+CASES = [
+    # name, system factory, theta, eps, n_leaf, n_grp
+    ("ring4096", lambda: inputs.ring(4096, 0), 0.5, 1e-3, 8, 64),
+    ("ring3001_ragged", lambda: inputs.ring(3001, 5), 0.6, 1e-3, 8, 32),
+    ("plummer5000_g256", lambda: inputs.plummer(5000, 7), 0.7, 1e-2, 8, 256),
+    ("ring2000_theta0", lambda: inputs.ring(2000, 9), 0.0, 1e-3, 8, 64),
+    ("ring777_leaf1", lambda: inputs.ring(777, 3), 0.4, 1e-3, 1, 16),
+    ("single_particle", lambda: inputs.ring(1, 2), 0.5, 1e-3, 8, 64),
+    ("eight_particles", lambda: inputs.ring(8, 2), 0.5, 1e-3, 8, 64),
+    ("ring20000_g300", lambda: inputs.ring(20000, 11), 0.5, 1e-4, 8, 300),
+]
+
+
+def _coincident():
+    s = inputs.ring(600, 4)
+    for a in (s.x, s.y, s.z):
+        a[:40] = a[0]                    # 40 identical points: a level-21 leaf above n_leaf
+    return s
+
+
+CASES.append(("coincident40", _coincident, 0.5, 1e-3, 8, 32))
+
+
+@pytest.mark.parametrize("name,make,theta,eps,n_leaf,n_grp", CASES, ids=[c[0] for c in CASES])
+def test_structures_and_fp64_forces(torch_cuda, name, make, theta, eps, n_leaf, n_grp):
+    torch = torch_cuda
+    _log(f"[gpu] structures+fp64 {name}")
+    s = make()
+    st = oracle.BHState(s.x, s.y, s.z, s.m, theta, n_leaf, n_grp)
+    ctx, dev = _gpu_build(torch, [s], theta, eps, n_leaf, n_grp, precision=0)
+    _compare_structures(ctx, st, s.n)
+    out = {k: torch.zeros(s.n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az", "pot")}
+    ctx.forces([out])
+    torch.cuda.synchronize()
+    ax, ay, az, pot, mag = st.accel(s.x, s.y, s.z, s.m, eps)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    err = np.sqrt((g["ax"] - ax) ** 2 + (g["ay"] - ay) ** 2 + (g["az"] - az) ** 2)
+    assert np.all(err <= 1e-12 * mag + 1e-300), f"max err/mag {np.max(err / mag)}"
+    np.testing.assert_allclose(g["pot"], pot, rtol=1e-12)
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,make,theta,eps,n_leaf,n_grp", CASES[:3] + CASES[-2:],
+                         ids=[c[0] for c in CASES[:3] + CASES[-2:]])
+def test_fp32_relative_forces(torch_cuda, name, make, theta, eps, n_leaf, n_grp):
+    torch = torch_cuda
+    _log(f"[gpu] fp32 {name}")
+    s = make()
+    st = oracle.BHState(s.x, s.y, s.z, s.m, theta, n_leaf, n_grp)
+    ctx, dev = _gpu_build(torch, [s], theta, eps, n_leaf, n_grp, precision=1)
+    _compare_structures(ctx, st, s.n)
+    out = {k: torch.zeros(s.n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+    ctx.forces([out])
+    torch.cuda.synchronize()
+    ax, ay, az, pot, mag = st.accel(s.x, s.y, s.z, s.m, eps)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    rel = np.sqrt((g["ax"] - ax) ** 2 + (g["ay"] - ay) ** 2 + (g["az"] - az) ** 2) / np.sqrt(ax ** 2 + ay ** 2 + az ** 2)
+    _log(f"    fp32 rel err: median {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e} max {rel.max():.2e}")
+    assert np.median(rel) <= 1e-5
+    ctx.close()
+
+
+def test_batched_systems_match_single(torch_cuda):
+    """Several systems in one context: each system's structures and forces
+    equal the oracle run on that system alone."""
+    torch = torch_cuda
+    _log("[gpu] batched systems")
+    systems = [inputs.plummer(n, 300 + k) for k, n in enumerate((1500, 37, 4100, 900))]
+    theta, eps = 0.6, 1e-2
+    ctx, dev = _gpu_build(torch, systems, theta, eps, 8, 64, precision=0)
+    outs = [{k: torch.zeros(s.n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")} for s in systems]
+    ctx.forces(outs)
+    torch.cuda.synchronize()
+    nodes = ctx.export("nodes")
+    keys = ctx.export("keys")
+    perm = ctx.export("perm")
+    off = np.concatenate([[0], np.cumsum([s.n for s in systems])])
+    for k, s in enumerate(systems):
+        st = oracle.BHState(s.x, s.y, s.z, s.m, theta, 8, 64)
+        np.testing.assert_array_equal(keys[off[k]:off[k + 1]], st.skey)
+        np.testing.assert_array_equal(perm[off[k]:off[k + 1]], st.perm)
+        mine = nodes[nodes[:, 1] == k]
+        np.testing.assert_array_equal(mine[:, 0], st.tree["level"])
+        np.testing.assert_array_equal(mine[:, 2].astype(np.uint64), st.tree["prefix"])
+        np.testing.assert_array_equal(mine[:, 3] - off[k], st.tree["begin"])
+        np.testing.assert_array_equal(mine[:, 4], st.tree["count"])
+        ax, ay, az, _, mag = st.accel(s.x, s.y, s.z, s.m, eps)
+        g = {q: v.cpu().numpy() for q, v in outs[k].items()}
+        err = np.sqrt((g["ax"] - ax) ** 2 + (g["ay"] - ay) ** 2 + (g["az"] - az) ** 2)
+        assert np.all(err <= 1e-12 * mag)
+    ctx.close()
+
+
+def test_nonfinite_rejected(torch_cuda):
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    s = inputs.ring(500, 1)
+    s.x[17] = np.nan
+    ctx = _ctx(0.5, 1e-3)
+    with pytest.raises(bh.BHError) as e:
+        ctx.build_tree([bh.to_device(s)])
+    assert e.value.status == bh.BH_EINVAL
+    with pytest.raises(bh.BHError) as e:
+        ctx.forces(None)
+    assert e.value.status == bh.BH_ESTATE
+    ctx.close()
+
+
+def test_step_fp64_matches_oracle_trajectory(torch_cuda):
+    """KDK with list reuse (rebuild every 3 steps) against the oracle's
+    trajectory: FP64 forces agree to ~1e-13, so positions stay within 1e-10."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log("[gpu] step fp64")
+    s = inputs.ring(3000, 12, central_mass=1.0)
+    theta, eps, dt, n = 0.5, 1e-3, 1e-3, 7
+    ref = oracle.kdk(s.x, s.y, s.z, s.vx, s.vy, s.vz, s.m, dt, n, eps, central_mass=1.0, theta=theta,
+                     n_grp=64, rebuild_every=3)
+    ctx = _ctx(theta, eps, central_mass=1.0)
+    dev = bh.to_device(s)
+    ctx.step([dev], dt, n, rebuild_every=3)
+    torch.cuda.synchronize()
+    for k, key in enumerate(("x", "y", "z", "vx", "vy", "vz")):
+        got = dev[key].cpu().numpy()
+        assert np.max(np.abs(got - ref[k])) < 1e-10, key
+    ctx.close()
