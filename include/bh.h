@@ -112,6 +112,9 @@ typedef struct {
     int64_t interactions;     /* sum over groups of n_g * (particles in pp leaves + pc nodes) */
     int32_t n_group_used;     /* group size in effect */
     int32_t lists_valid;      /* 1 once bh_make_lists has run on the current tree */
+    int64_t interactions_evaluated;  /* running total over every force evaluation of the context */
+    int64_t force_evaluations;       /* running count of force evaluations */
+    int64_t tree_builds;             /* running count of tree builds */
 } bh_sizes;
 
 /* What bh_export copies out (to HOST memory; the call synchronises `stream`).
@@ -123,8 +126,8 @@ typedef enum {
     BH_EXPORT_NODES = 2,      /* per node, int64[n_nodes][8]: level, system, prefix, begin,
                                  count, first_child, n_child, is_group */
     BH_EXPORT_MOMENTS = 3,    /* double[n_nodes][4]: com x, y, z, mass */
-    BH_EXPORT_GROUPS = 4,     /* per group, int64[n_groups][8]: node, begin, count, box lo xyz,
-                                 plus box hi xyz in a second block: see bh_export_groups */
+    BH_EXPORT_GROUPS = 4,     /* per group (ascending first particle), int64[n_groups][4]:
+                                 node, begin, count, system; boxes: bh_export_groups */
     BH_EXPORT_LISTS = 5,      /* CSR: int64 pc_off[n_groups+1], int64 pp_off[n_groups+1],
                                  uint32 pc[n_pc], uint32 pp[n_pp], packed in that order,
                                  each list in ascending node id */
@@ -166,6 +169,31 @@ bh_status bh_forces(bh_ctx *ctx, const bh_accel *out, void *stream);
  * every system are updated in place. */
 bh_status bh_step(bh_ctx *ctx, const bh_system *sys, int32_t n_sys, double dt,
                   int32_t n_steps, int32_t rebuild_every, void *stream);
+
+/* Continue integrating the systems of the last bh_step (or of bh_build_tree
+ * + bh_make_lists + bh_forces, with velocities) from the context's internal
+ * state: n_steps more kick-drift-kick steps, the rebuild schedule carried on
+ * from the previous call (a build every rebuild_every force evaluations).
+ * The caller's arrays of that call are written at the end, and must not be
+ * changed by the caller in between (use bh_step to start over).  BH_ESTATE
+ * if there is no state to continue. */
+bh_status bh_step_continue(bh_ctx *ctx, double dt, int32_t n_steps, int32_t rebuild_every, void *stream);
+
+/* Direct summation (the exact sum the tree approximates) in FP64 for the
+ * targets of one system: for t < n_targets, i = targets[t],
+ *   a[t] = sum_j G m_j (x_j - x_i) / (|x_j - x_i|^2 + eps^2)^(3/2),
+ * j over all n particles of sys (caller order; j = i adds nothing when
+ * eps > 0 and is skipped when eps = 0).  targets, ax, ay, az: device arrays
+ * of n_targets entries.  Uses the context's G and eps; independent of the
+ * tree.  Serves as the error judge of the approximation. */
+bh_status bh_direct_sum(bh_ctx *ctx, const bh_system *sys, const int64_t *targets, int64_t n_targets,
+                        double *ax, double *ay, double *az, void *stream);
+
+/* Force-kernel device time accumulated over the launches since the last
+ * reset, from HIP events recorded around each launch on its stream
+ * (synchronises those events).  reset != 0 clears the accumulator after
+ * reading. */
+bh_status bh_force_timing(bh_ctx *ctx, double *total_ms, int64_t *launches, int32_t reset);
 
 bh_status bh_query(const bh_ctx *ctx, bh_sizes *out);
 

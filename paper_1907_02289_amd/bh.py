@@ -20,7 +20,8 @@ EXPORT = dict(keys=0, perm=1, nodes=2, moments=3, groups=4, lists=5, acc_sorted=
 STAGES = ("keys_sort", "tree", "moments", "groups", "walk", "forces", "integrate", "step")
 
 SYMBOLS = ("bh_create", "bh_destroy", "bh_set_params", "bh_build_tree", "bh_make_lists", "bh_forces",
-           "bh_step", "bh_query", "bh_export", "bh_export_groups", "bh_stage_times", "bh_last_error")
+           "bh_step", "bh_step_continue", "bh_direct_sum", "bh_force_timing", "bh_query", "bh_export",
+           "bh_export_groups", "bh_stage_times", "bh_last_error")
 
 
 class Params(C.Structure):
@@ -41,7 +42,9 @@ class Accel(C.Structure):
 class Sizes(C.Structure):
     _fields_ = [("n_particles", C.c_int64), ("n_systems", C.c_int32), ("max_level", C.c_int32),
                 ("n_nodes", C.c_int64), ("n_groups", C.c_int64), ("n_pc", C.c_int64), ("n_pp", C.c_int64),
-                ("interactions", C.c_int64), ("n_group_used", C.c_int32), ("lists_valid", C.c_int32)]
+                ("interactions", C.c_int64), ("n_group_used", C.c_int32), ("lists_valid", C.c_int32),
+                ("interactions_evaluated", C.c_int64), ("force_evaluations", C.c_int64),
+                ("tree_builds", C.c_int64)]
 
 
 _lib = None
@@ -65,6 +68,9 @@ def load_library(path: str = LIB_PATH):
     L.bh_make_lists.argtypes = [vp, vp]
     L.bh_forces.argtypes = [vp, C.POINTER(Accel), vp]
     L.bh_step.argtypes = [vp, C.POINTER(System), i32, dbl, i32, i32, vp]
+    L.bh_step_continue.argtypes = [vp, dbl, i32, i32, vp]
+    L.bh_direct_sum.argtypes = [vp, C.POINTER(System), vp, C.c_int64, vp, vp, vp, vp]
+    L.bh_force_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
     L.bh_query.argtypes = [vp, C.POINTER(Sizes)]
     L.bh_export.argtypes = [vp, i32, vp, vp]
     L.bh_export_groups.argtypes = [vp, vp, vp, vp]
@@ -161,6 +167,24 @@ class Context:
         arr = self._systems(systems)
         self._check(self.L.bh_step(self.h, arr, len(systems), float(dt), int(n_steps), int(rebuild_every),
                                    _stream()))
+
+    def step_continue(self, dt, n_steps, rebuild_every=1):
+        self._check(self.L.bh_step_continue(self.h, float(dt), int(n_steps), int(rebuild_every), _stream()))
+
+    def direct_sum(self, system, targets, out):
+        """FP64 direct sum for the targets (int64 CUDA tensor) of one system;
+        out: dict of ax, ay, az tensors of len(targets)."""
+        import torch
+        assert targets.is_cuda and targets.dtype == torch.int64 and targets.is_contiguous()
+        arr = self._systems([system])
+        self._check(self.L.bh_direct_sum(self.h, arr, C.c_void_p(targets.data_ptr()), targets.numel(),
+                                         _ptr(out["ax"]), _ptr(out["ay"]), _ptr(out["az"]), _stream()))
+
+    def force_timing(self, reset=True):
+        """(total ms, launches) of the force kernel since the last reset."""
+        ms, k = C.c_double(), C.c_int64()
+        self._check(self.L.bh_force_timing(self.h, C.byref(ms), C.byref(k), 1 if reset else 0))
+        return ms.value, k.value
 
     def query(self):
         s = Sizes()

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbh.so")
-SOURCES = ["bh_api.hip", "bh_sort.hip", "bh_tree.hip", "bh_walk.hip", "bh_force.hip", "bh_integrate.hip"]
+SOURCES = ["bh_api.hip", "bh_sort.hip", "bh_tree.hip", "bh_walk.hip", "bh_force.hip", "bh_integrate.hip",
+           "bh_direct.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

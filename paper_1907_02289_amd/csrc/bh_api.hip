@@ -64,6 +64,15 @@ struct bh_ctx {
 
     hipEvent_t ev0[EV_N] = {}, ev1[EV_N] = {};
     bool ev_used[EV_N] = {};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> force_ev;   // one pair per force launch
+    size_t force_ev_used = 0;
+
+    // running totals and integration state
+    int64_t interactions_evaluated = 0, force_evaluations = 0, tree_builds = 0;
+    bool state_valid = false;     // sorted x, v, a ready for bh_step_continue
+    bool have_vel = false;
+    int age = 0;                  // force evaluations done with the current lists
+    DevBuf direct_part;
 
     DevState d{};
 };
@@ -155,9 +164,9 @@ void refresh_state(bh_ctx *c) {
     d.g_lo = P<int4>(c->g_lo);
     d.g_hi = P<int4>(c->g_hi);
     d.g_cen = P<double4>(c->g_cen);
-    d.g_pc_off = P<uint32_t>(c->g_pc_off);
+    d.g_pc_off = P<unsigned long long>(c->g_pc_off);
     d.g_pc_len = P<uint32_t>(c->g_pc_len);
-    d.g_pp_off = P<uint32_t>(c->g_pp_off);
+    d.g_pp_off = P<unsigned long long>(c->g_pp_off);
     d.g_pp_len = P<uint32_t>(c->g_pp_len);
     d.g_cost = P<unsigned long long>(c->g_cost);
     d.order = P<uint32_t>(c->order);
@@ -253,9 +262,9 @@ bh_status ensure_particles(bh_ctx *c, uint32_t n) {
     HIPCHK(c, grow(c->g_lo, (size_t)cap * sizeof(int4)));
     HIPCHK(c, grow(c->g_hi, (size_t)cap * sizeof(int4)));
     HIPCHK(c, grow(c->g_cen, d4));
-    HIPCHK(c, grow(c->g_pc_off, u4));
+    HIPCHK(c, grow(c->g_pc_off, u8));
     HIPCHK(c, grow(c->g_pc_len, u4));
-    HIPCHK(c, grow(c->g_pp_off, u4));
+    HIPCHK(c, grow(c->g_pp_off, u8));
     HIPCHK(c, grow(c->g_pp_len, u4));
     HIPCHK(c, grow(c->g_cost, u8));
     HIPCHK(c, grow(c->order, u4));
@@ -345,6 +354,8 @@ bh_status rebuild(bh_ctx *c, hipStream_t s, bool from_caller) {
     c->n_groups = c->h_cnt->n_groups;
     c->tree_valid = true;
     c->lists_valid = false;
+    c->tree_builds += 1;
+    c->age = 0;
     return BH_OK;
 }
 
@@ -385,9 +396,25 @@ bh_status make_lists(bh_ctx *c, hipStream_t s) {
 int force_blocks(const bh_ctx *c) { return c->n_cu * 8; }
 
 bh_status run_forces(bh_ctx *c, hipStream_t s, bool pot) {
+    if (c->force_ev_used == c->force_ev.size()) {
+        if (c->force_ev.size() >= 65536) {
+            c->force_ev_used = 0;                    // drop the oldest window
+        } else {
+            hipEvent_t a, b;
+            HIPCHK(c, hipEventCreate(&a));
+            HIPCHK(c, hipEventCreate(&b));
+            c->force_ev.emplace_back(a, b);
+        }
+    }
+    auto &pr = c->force_ev[c->force_ev_used++];
     ev_begin(c, EV_FORCE, s);
+    HIPCHK(c, hipEventRecord(pr.first, s));
     bhk::forces(c->d, c->n_groups, c->P.precision == BH_FP32_REL, pot, force_blocks(c), s);
+    HIPCHK(c, hipEventRecord(pr.second, s));
     ev_end(c, EV_FORCE, s);
+    c->interactions_evaluated += (int64_t)c->interactions;
+    c->force_evaluations += 1;
+    c->age += 1;
     return BH_OK;
 }
 
@@ -474,7 +501,7 @@ bh_status bh_destroy(bh_ctx *c) {
                      &c->nd_first, &c->nd_meta, &c->nd_walk, &c->nd_mom, &c->nd_quad, &c->tmp_a, &c->tmp_b,
                      &c->gmark, &c->grp, &c->g_lo, &c->g_hi, &c->g_cen, &c->g_pc_off, &c->g_pc_len,
                      &c->g_pp_off, &c->g_pp_len, &c->g_cost, &c->order, &c->gkey_a, &c->gkey_b, &c->gval_a,
-                     &c->gval_b, &c->pc_pool, &c->pp_pool, &c->walk_scratch, &c->counters};
+                     &c->gval_b, &c->pc_pool, &c->pp_pool, &c->walk_scratch, &c->counters, &c->direct_part};
     for (DevBuf *b : all) release(*b);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
     if (c->h_systab) (void)hipHostFree(c->h_systab);
@@ -483,6 +510,10 @@ bh_status bh_destroy(bh_ctx *c) {
     for (int k = 0; k < EV_N; ++k) {
         if (c->ev0[k]) (void)hipEventDestroy(c->ev0[k]);
         if (c->ev1[k]) (void)hipEventDestroy(c->ev1[k]);
+    }
+    for (auto &pr : c->force_ev) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
     }
     delete c;
     return BH_OK;
@@ -503,8 +534,10 @@ bh_status bh_set_params(bh_ctx *c, const bh_params *p) {
 bh_status bh_build_tree(bh_ctx *c, const bh_system *sys, int32_t n_sys, void *stream) {
     if (!c) return BH_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    c->tree_valid = c->lists_valid = false;
+    c->tree_valid = c->lists_valid = c->state_valid = false;
     STCHK(set_systems(c, sys, n_sys, s));
+    c->have_vel = true;
+    for (int k = 0; k < n_sys; ++k) c->have_vel &= sys[k].vx && sys[k].vy && sys[k].vz;
     return rebuild(c, s, true);
 }
 
@@ -525,6 +558,7 @@ bh_status bh_forces(bh_ctx *c, const bh_accel *out, void *stream) {
         }
     refresh_state(c);
     STCHK(run_forces(c, s, pot || !out));
+    c->state_valid = true;
     if (out) {
         STCHK(wait_tables(c));
         for (int k = 0; k < c->n_sys; ++k)
@@ -539,26 +573,21 @@ bh_status bh_forces(bh_ctx *c, const bh_accel *out, void *stream) {
     return BH_OK;
 }
 
-bh_status bh_step(bh_ctx *c, const bh_system *sys, int32_t n_sys, double dt, int32_t n_steps,
-                  int32_t rebuild_every, void *stream) {
-    if (!c) return BH_EINVAL;
-    if (!std::isfinite(dt) || n_steps < 0 || rebuild_every < 1) return fail(c, BH_EINVAL, "bad step arguments");
-    for (int k = 0; sys && k < n_sys; ++k)
-        if (!sys[k].vx || !sys[k].vy || !sys[k].vz) return fail(c, BH_EINVAL, "bh_step needs velocities");
-    hipStream_t s = (hipStream_t)stream;
-    ev_begin(c, EV_STEP, s);
-    c->tree_valid = c->lists_valid = false;
-    STCHK(set_systems(c, sys, n_sys, s));
-    STCHK(rebuild(c, s, true));
-    STCHK(make_lists(c, s));
-    refresh_state(c);
-    STCHK(run_forces(c, s, false));
+}  // extern "C"
+
+namespace {
+
+// The integration loop shared by bh_step and bh_step_continue: kick-drift,
+// then a new tree and lists when the current lists have served
+// rebuild_every force evaluations, else moments refreshed on the same tree
+// (Sec. 4.2, list-reusing steps), then forces and the closing kick.
+bh_status integrate(bh_ctx *c, double dt, int32_t n_steps, int32_t rebuild_every, hipStream_t s) {
     const double h = 0.5 * dt;
     for (int k = 0; k < n_steps; ++k) {
         ev_begin(c, EV_INTEG, s);
         bhk::kick_drift(c->d, h, dt, s);
         ev_end(c, EV_INTEG, s);
-        if ((k + 1) % rebuild_every == 0) {
+        if (c->age >= rebuild_every) {
             STCHK(rebuild(c, s, false));
             STCHK(make_lists(c, s));
         } else {
@@ -571,8 +600,76 @@ bh_status bh_step(bh_ctx *c, const bh_system *sys, int32_t n_sys, double dt, int
         bhk::kick(c->d, h, s);
     }
     bhk::scatter_state(c->d, s);
-    ev_end(c, EV_STEP, s);
     HIPCHK(c, hipGetLastError());
+    return BH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bh_status bh_step(bh_ctx *c, const bh_system *sys, int32_t n_sys, double dt, int32_t n_steps,
+                  int32_t rebuild_every, void *stream) {
+    if (!c) return BH_EINVAL;
+    if (!std::isfinite(dt) || n_steps < 0 || rebuild_every < 1) return fail(c, BH_EINVAL, "bad step arguments");
+    for (int k = 0; sys && k < n_sys; ++k)
+        if (!sys[k].vx || !sys[k].vy || !sys[k].vz) return fail(c, BH_EINVAL, "bh_step needs velocities");
+    hipStream_t s = (hipStream_t)stream;
+    ev_begin(c, EV_STEP, s);
+    c->tree_valid = c->lists_valid = c->state_valid = false;
+    STCHK(set_systems(c, sys, n_sys, s));
+    STCHK(rebuild(c, s, true));
+    STCHK(make_lists(c, s));
+    refresh_state(c);
+    STCHK(run_forces(c, s, false));
+    c->have_vel = true;
+    c->state_valid = true;
+    bh_status st = integrate(c, dt, n_steps, rebuild_every, s);
+    if (st != BH_OK) c->state_valid = false;
+    ev_end(c, EV_STEP, s);
+    return st;
+}
+
+bh_status bh_step_continue(bh_ctx *c, double dt, int32_t n_steps, int32_t rebuild_every, void *stream) {
+    if (!c) return BH_EINVAL;
+    if (!std::isfinite(dt) || n_steps < 0 || rebuild_every < 1) return fail(c, BH_EINVAL, "bad step arguments");
+    if (!c->state_valid || !c->have_vel || !c->lists_valid)
+        return fail(c, BH_ESTATE, "bh_step_continue: no integration state (call bh_step first)");
+    hipStream_t s = (hipStream_t)stream;
+    ev_begin(c, EV_STEP, s);
+    refresh_state(c);
+    bh_status st = integrate(c, dt, n_steps, rebuild_every, s);
+    if (st != BH_OK) c->state_valid = false;
+    ev_end(c, EV_STEP, s);
+    return st;
+}
+
+bh_status bh_direct_sum(bh_ctx *c, const bh_system *sys, const int64_t *targets, int64_t n_targets, double *ax,
+                        double *ay, double *az, void *stream) {
+    if (!c || !sys || !targets || !ax || !ay || !az) return BH_EINVAL;
+    if (sys->n < 1 || !sys->x || !sys->y || !sys->z || !sys->m || n_targets < 0 || sys->n >= (1ll << 31))
+        return fail(c, BH_EINVAL, "bh_direct_sum: bad system or targets");
+    if (n_targets == 0) return BH_OK;
+    size_t need = bhk::direct_scratch_bytes(n_targets);
+    HIPCHK(c, grow(c->direct_part, need));
+    bhk::direct_sum(sys->x, sys->y, sys->z, sys->m, sys->n, targets, n_targets, c->P.eps * c->P.eps, c->P.G,
+                    ax, ay, az, P<double>(c->direct_part), (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return BH_OK;
+}
+
+bh_status bh_force_timing(bh_ctx *c, double *total_ms, int64_t *launches, int32_t reset) {
+    if (!c) return BH_EINVAL;
+    double tot = 0.0;
+    for (size_t k = 0; k < c->force_ev_used; ++k) {
+        HIPCHK(c, hipEventSynchronize(c->force_ev[k].second));
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->force_ev[k].first, c->force_ev[k].second));
+        tot += t;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)c->force_ev_used;
+    if (reset) c->force_ev_used = 0;
     return BH_OK;
 }
 
@@ -588,6 +685,9 @@ bh_status bh_query(const bh_ctx *c, bh_sizes *o) {
     o->interactions = c->lists_valid ? (int64_t)c->interactions : 0;
     o->n_group_used = c->n_grp_used;
     o->lists_valid = c->lists_valid ? 1 : 0;
+    o->interactions_evaluated = c->interactions_evaluated;
+    o->force_evaluations = c->force_evaluations;
+    o->tree_builds = c->tree_builds;
     return BH_OK;
 }
 
@@ -652,11 +752,12 @@ bh_status bh_export(bh_ctx *c, int32_t what, void *dst, void *stream) {
     }
     case BH_EXPORT_LISTS: {
         if (!c->lists_valid) return fail(c, BH_ESTATE, "no lists");
-        std::vector<uint32_t> po(ng), pl(ng), qo(ng), ql(ng);
+        std::vector<uint64_t> po(ng), qo(ng);
+        std::vector<uint32_t> pl(ng), ql(ng);
         std::vector<uint32_t> pcp(c->n_pc), ppp(c->n_pp);
-        HIPCHK(c, hipMemcpy(po.data(), c->g_pc_off.p, ng * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(po.data(), c->g_pc_off.p, ng * 8, hipMemcpyDeviceToHost));
         HIPCHK(c, hipMemcpy(pl.data(), c->g_pc_len.p, ng * 4, hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(qo.data(), c->g_pp_off.p, ng * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(qo.data(), c->g_pp_off.p, ng * 8, hipMemcpyDeviceToHost));
         HIPCHK(c, hipMemcpy(ql.data(), c->g_pp_len.p, ng * 4, hipMemcpyDeviceToHost));
         if (c->n_pc) HIPCHK(c, hipMemcpy(pcp.data(), c->pc_pool.p, c->n_pc * 4, hipMemcpyDeviceToHost));
         if (c->n_pp) HIPCHK(c, hipMemcpy(ppp.data(), c->pp_pool.p, c->n_pp * 4, hipMemcpyDeviceToHost));

@@ -97,8 +97,8 @@ __global__ void __launch_bounds__(FT) k_force(DevState d, uint32_t ng) {
         const uint32_t g = d.order[item];
         const GroupInfo gi = d.grp[g];
         const double4 cen = d.g_cen[g];
-        const uint32_t pc0 = d.g_pc_off[g], npc = d.g_pc_len[g];
-        const uint32_t pp0 = d.g_pp_off[g], npp = d.g_pp_len[g];
+        const unsigned long long pc0 = d.g_pc_off[g], pp0 = d.g_pp_off[g];
+        const uint32_t npc = d.g_pc_len[g], npp = d.g_pp_len[g];
 
         for (uint32_t ib = 0; ib < gi.count; ib += FT) {
             const uint32_t nb = min((uint32_t)FT, gi.count - ib);

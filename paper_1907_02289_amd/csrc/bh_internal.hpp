@@ -153,7 +153,8 @@ struct DevState {
     int4 *g_lo, *g_hi;             // grid box, half-open
     double4 *g_cen;
     // lists
-    uint32_t *g_pc_off, *g_pc_len, *g_pp_off, *g_pp_len;
+    unsigned long long *g_pc_off, *g_pp_off;   // list starts in the pools (64-bit: pools exceed 2^32)
+    uint32_t *g_pc_len, *g_pp_len;
     unsigned long long *g_cost;    // interactions of the group
     uint32_t *order;               // groups by descending cost
     uint32_t *pc_pool, *pp_pool;
@@ -197,6 +198,12 @@ void kick_drift(const DevState &d, double h, double dt, hipStream_t s);
 void kick(const DevState &d, double h, hipStream_t s);
 void scatter_state(const DevState &d, hipStream_t s);
 void scatter_acc(const DevState &d, const AccPtr *tab, hipStream_t s);
+
+// FP64 direct summation for sampled targets (bh_direct.hip)
+size_t direct_scratch_bytes(int64_t n_targets);
+void direct_sum(const double *x, const double *y, const double *z, const double *m, int64_t n,
+                const int64_t *targets, int64_t nt, double eps2, double G, double *ax, double *ay, double *az,
+                double *scratch, hipStream_t s);
 
 // exclusive scan of n uint32 (n from *n_dev when n_dev != nullptr, else n_host);
 // out may alias in.  *total (if non-null) receives the sum.  tmp: >= 1024 words.

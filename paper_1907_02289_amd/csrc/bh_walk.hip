@@ -129,9 +129,9 @@ __global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
         }
         const unsigned long long cost = (unsigned long long)gi.count * (pp_particles + npc);
         if (lane == 0) {
-            d.g_pc_off[g] = fit ? (uint32_t)at_pc : 0u;
+            d.g_pc_off[g] = fit ? at_pc : 0ull;
             d.g_pc_len[g] = fit ? npc : 0u;
-            d.g_pp_off[g] = fit ? (uint32_t)at_pp : 0u;
+            d.g_pp_off[g] = fit ? at_pp : 0ull;
             d.g_pp_len[g] = fit ? npp : 0u;
             d.g_cost[g] = cost;
             atomicAdd(&d.cnt->interactions, cost);

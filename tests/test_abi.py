@@ -1,0 +1,44 @@
+"""The C-ABI library loads and exports every function include/bh.h declares
+(no GPU work: only symbol lookup), and the binding knows each of them."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bh.h")
+LIB = os.path.join(ROOT, "paper_1907_02289_amd", "libbh.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:bh_status|const char \*)\s*(bh_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("bh_build_tree", "bh_make_lists", "bh_forces", "bh_step"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        from paper_1907_02289_amd import build
+        build.build()
+    lib = ctypes.CDLL(LIB)
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_lists_every_symbol():
+    from paper_1907_02289_amd import bh
+    assert sorted(bh.SYMBOLS) == declared()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr

@@ -213,3 +213,43 @@ def test_step_fp64_matches_oracle_trajectory(torch_cuda):
         got = dev[key].cpu().numpy()
         assert np.max(np.abs(got - ref[k])) < 1e-10, key
     ctx.close()
+
+
+def test_direct_sum_judge_matches_oracle(torch_cuda):
+    """The GPU FP64 direct sum (the error judge) against the oracle's."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log("[gpu] direct sum")
+    s = inputs.ring(70001, 13)
+    tg = np.sort(np.random.default_rng(1).choice(s.n, 256, replace=False)).astype(np.int64)
+    ctx = _ctx(0.5, 1e-3)
+    dev = bh.to_device(s)
+    out = {k: torch.zeros(tg.size, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+    ctx.direct_sum(dev, torch.as_tensor(tg, device="cuda"), out)
+    torch.cuda.synchronize()
+    ax, ay, az, _ = oracle.direct(s.x, s.y, s.z, s.m, 1e-3, targets=tg)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    err = np.sqrt((g["ax"] - ax) ** 2 + (g["ay"] - ay) ** 2 + (g["az"] - az) ** 2)
+    assert np.all(err <= 1e-13 * np.sqrt(ax ** 2 + ay ** 2 + az ** 2))
+    ctx.close()
+
+
+def test_step_continue_is_the_same_trajectory(torch_cuda):
+    """bh_step over 6 steps == bh_step over 2 + bh_step_continue over 4
+    (same operations in the same order: bit-identical), FP32 interactions."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log("[gpu] step continue")
+    s = inputs.ring(5000, 14, central_mass=1.0)
+    a, b = bh.to_device(s), bh.to_device(s)
+    c1 = _ctx(0.5, 1e-3, n_grp=128, precision=1, central_mass=1.0)
+    c1.step([a], 1e-3, 6, rebuild_every=4)
+    c2 = _ctx(0.5, 1e-3, n_grp=128, precision=1, central_mass=1.0)
+    c2.step([b], 1e-3, 2, rebuild_every=4)
+    c2.step_continue(1e-3, 4, rebuild_every=4)
+    torch.cuda.synchronize()
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert torch.equal(a[k], b[k]), k
+    assert c1.query()["tree_builds"] == 2 and c2.query()["tree_builds"] == 2
+    c1.close()
+    c2.close()
