@@ -84,7 +84,11 @@ typedef struct {
     int32_t precision;     /* bh_precision */
     int32_t criterion;     /* bh_criterion */
     double theta_min, theta_max, tau;   /* learned rule only */
+    int32_t flags;         /* BH_FLAG_* bits */
 } bh_params;
+
+/* bh_params.flags: replay list-reusing steps eagerly instead of from a HIP graph. */
+#define BH_FLAG_NO_GRAPH 1
 
 /* One system: device arrays of n FP64 values each, caller order.
  * bh_step updates x,y,z,vx,vy,vz in place; m is read only. */
@@ -194,6 +198,16 @@ bh_status bh_direct_sum(bh_ctx *ctx, const bh_system *sys, const int64_t *target
  * (synchronises those events).  reset != 0 clears the accumulator after
  * reading. */
 bh_status bh_force_timing(bh_ctx *ctx, double *total_ms, int64_t *launches, int32_t reset);
+
+/* Group-size autotuner (the scheduling of Sec. 4.6 leaves the group size
+ * free): for each candidate group size, regroup the current tree, walk and
+ * evaluate forces once, timing both with HIP events; keep the candidate with
+ * the smallest force time + walk time / rebuild_every and leave its lists in
+ * place.  Speed at the context's theta only: a larger group is also more
+ * accurate at equal theta, which this call does not weigh.  Requires
+ * bh_build_tree.  *chosen (may be NULL) receives the group size. */
+bh_status bh_autotune(bh_ctx *ctx, const int32_t *candidates, int32_t n_candidates, int32_t rebuild_every,
+                      int32_t *chosen, void *stream);
 
 bh_status bh_query(const bh_ctx *ctx, bh_sizes *out);
 

@@ -15,20 +15,21 @@ LIB_PATH = os.path.join(HERE, "libbh.so")
 
 BH_OK, BH_EINVAL, BH_ENOMEM, BH_EHIP, BH_ESTATE, BH_ECAPACITY = 0, -1, -2, -3, -4, -5
 FP64, FP32_REL = 0, 1
+FLAG_NO_GRAPH = 1
 GEOMETRIC, LEARNED = 0, 1
 EXPORT = dict(keys=0, perm=1, nodes=2, moments=3, groups=4, lists=5, acc_sorted=6, sorted_pos=7)
 STAGES = ("keys_sort", "tree", "moments", "groups", "walk", "forces", "integrate", "step")
 
 SYMBOLS = ("bh_create", "bh_destroy", "bh_set_params", "bh_build_tree", "bh_make_lists", "bh_forces",
            "bh_step", "bh_step_continue", "bh_direct_sum", "bh_force_timing", "bh_query", "bh_export",
-           "bh_export_groups", "bh_stage_times", "bh_last_error")
+           "bh_export_groups", "bh_stage_times", "bh_autotune", "bh_last_error")
 
 
 class Params(C.Structure):
     _fields_ = [("theta", C.c_double), ("eps", C.c_double), ("G", C.c_double), ("central_mass", C.c_double),
                 ("n_leaf", C.c_int32), ("n_group", C.c_int32), ("precision", C.c_int32),
                 ("criterion", C.c_int32), ("theta_min", C.c_double), ("theta_max", C.c_double),
-                ("tau", C.c_double)]
+                ("tau", C.c_double), ("flags", C.c_int32)]
 
 
 class System(C.Structure):
@@ -71,6 +72,7 @@ def load_library(path: str = LIB_PATH):
     L.bh_step_continue.argtypes = [vp, dbl, i32, i32, vp]
     L.bh_direct_sum.argtypes = [vp, C.POINTER(System), vp, C.c_int64, vp, vp, vp, vp]
     L.bh_force_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
+    L.bh_autotune.argtypes = [vp, C.POINTER(C.c_int32), i32, i32, C.POINTER(C.c_int32), vp]
     L.bh_query.argtypes = [vp, C.POINTER(Sizes)]
     L.bh_export.argtypes = [vp, i32, vp, vp]
     L.bh_export_groups.argtypes = [vp, vp, vp, vp]
@@ -106,10 +108,11 @@ class Context:
     """One library context (tree, lists and scratch on the current device)."""
 
     def __init__(self, theta=0.5, eps=1e-3, G=1.0, central_mass=0.0, n_leaf=8, n_group=64,
-                 precision=FP64, criterion=GEOMETRIC, theta_min=0.2, theta_max=1.0, tau=1e-3):
+                 precision=FP64, criterion=GEOMETRIC, theta_min=0.2, theta_max=1.0, tau=1e-3,
+                 use_graphs=True):
         self.L = load_library()
         self.params = Params(theta, eps, G, central_mass, n_leaf, n_group, precision, criterion,
-                             theta_min, theta_max, tau)
+                             theta_min, theta_max, tau, 0 if use_graphs else FLAG_NO_GRAPH)
         h = C.c_void_p()
         self._check(self.L.bh_create(C.byref(h), C.byref(self.params)), ctx=None)
         self.h = h
@@ -179,6 +182,12 @@ class Context:
         arr = self._systems([system])
         self._check(self.L.bh_direct_sum(self.h, arr, C.c_void_p(targets.data_ptr()), targets.numel(),
                                          _ptr(out["ax"]), _ptr(out["ay"]), _ptr(out["az"]), _stream()))
+
+    def autotune(self, candidates=(64, 128, 256, 512), rebuild_every=4):
+        arr = (C.c_int32 * len(candidates))(*candidates)
+        out = C.c_int32()
+        self._check(self.L.bh_autotune(self.h, arr, len(candidates), int(rebuild_every), C.byref(out), _stream()))
+        return out.value
 
     def force_timing(self, reset=True):
         """(total ms, launches) of the force kernel since the last reset."""

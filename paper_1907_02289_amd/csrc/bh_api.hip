@@ -74,6 +74,22 @@ struct bh_ctx {
     int age = 0;                  // force evaluations done with the current lists
     DevBuf direct_part;
 
+    // HIP graphs of the launch-bound part of a list-reusing step (kick-drift +
+    // the per-level moment refresh), replayed on an internal stream fenced
+    // with events against the caller's stream.  Two cached instances: the
+    // sorted buffers alternate between two allocations from one tree build to
+    // the next.
+    struct GraphEntry {
+        DevState key;
+        double h = 0, dt = 0;
+        hipGraphExec_t exec = nullptr;
+    };
+    GraphEntry graphs[2];
+    int graph_next = 0;
+    hipStream_t gs = nullptr;
+    hipEvent_t fence_a = nullptr, fence_b = nullptr;
+    int64_t graph_replays = 0, graph_captures = 0;
+
     DevState d{};
 };
 
@@ -483,6 +499,9 @@ bh_status bh_create(bh_ctx **out, const bh_params *p) {
               grow(c->counters, sizeof(DevCounters)) == hipSuccess;
     for (int k = 0; ok && k < EV_N; ++k)
         ok = hipEventCreate(&c->ev0[k]) == hipSuccess && hipEventCreate(&c->ev1[k]) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&c->fence_a, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&c->fence_b, hipEventDisableTiming) == hipSuccess;
     if (!ok || ensure_walk(c) != BH_OK) {
         bh_destroy(c);
         return BH_ENOMEM;
@@ -515,6 +534,11 @@ bh_status bh_destroy(bh_ctx *c) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
     }
+    for (auto &g : c->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (c->fence_a) (void)hipEventDestroy(c->fence_a);
+    if (c->fence_b) (void)hipEventDestroy(c->fence_b);
+    if (c->gs) (void)hipStreamDestroy(c->gs);
     delete c;
     return BH_OK;
 }
@@ -581,16 +605,61 @@ namespace {
 // then a new tree and lists when the current lists have served
 // rebuild_every force evaluations, else moments refreshed on the same tree
 // (Sec. 4.2, list-reusing steps), then forces and the closing kick.
+bool same_key(const bh_ctx::GraphEntry &g, const DevState &d, double h, double dt) {
+    return g.exec && g.h == h && g.dt == dt && std::memcmp(&g.key, &d, sizeof(DevState)) == 0;
+}
+
+// Kick-drift and moment refresh of a list-reusing step, from a cached graph.
+bh_status reuse_prefix_graph(bh_ctx *c, double h, double dt, hipStream_t s) {
+    bh_ctx::GraphEntry *hit = nullptr;
+    for (auto &g : c->graphs)
+        if (same_key(g, c->d, h, dt)) hit = &g;
+    if (!hit) {
+        hit = &c->graphs[c->graph_next];
+        c->graph_next ^= 1;
+        if (hit->exec) {
+            HIPCHK(c, hipGraphExecDestroy(hit->exec));
+            hit->exec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->gs, hipStreamCaptureModeThreadLocal));
+        bhk::kick_drift(c->d, h, dt, c->gs);
+        bhk::moments(c->d, c->gs);
+        HIPCHK(c, hipStreamEndCapture(c->gs, &graph));
+        hipError_t e = hipGraphInstantiate(&hit->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(c, e);
+        std::memcpy(&hit->key, &c->d, sizeof(DevState));
+        hit->h = h;
+        hit->dt = dt;
+        c->graph_captures += 1;
+    }
+    HIPCHK(c, hipEventRecord(c->fence_a, s));
+    HIPCHK(c, hipStreamWaitEvent(c->gs, c->fence_a, 0));
+    HIPCHK(c, hipGraphLaunch(hit->exec, c->gs));
+    HIPCHK(c, hipEventRecord(c->fence_b, c->gs));
+    HIPCHK(c, hipStreamWaitEvent(s, c->fence_b, 0));
+    c->graph_replays += 1;
+    return BH_OK;
+}
+
 bh_status integrate(bh_ctx *c, double dt, int32_t n_steps, int32_t rebuild_every, hipStream_t s) {
     const double h = 0.5 * dt;
+    const bool graphs = !(c->P.flags & BH_FLAG_NO_GRAPH);
     for (int k = 0; k < n_steps; ++k) {
-        ev_begin(c, EV_INTEG, s);
-        bhk::kick_drift(c->d, h, dt, s);
-        ev_end(c, EV_INTEG, s);
         if (c->age >= rebuild_every) {
+            ev_begin(c, EV_INTEG, s);
+            bhk::kick_drift(c->d, h, dt, s);
+            ev_end(c, EV_INTEG, s);
             STCHK(rebuild(c, s, false));
             STCHK(make_lists(c, s));
+        } else if (graphs) {
+            refresh_state(c);
+            STCHK(reuse_prefix_graph(c, h, dt, s));
         } else {
+            ev_begin(c, EV_INTEG, s);
+            bhk::kick_drift(c->d, h, dt, s);
+            ev_end(c, EV_INTEG, s);
             ev_begin(c, EV_MOM, s);
             bhk::moments(c->d, s);
             ev_end(c, EV_MOM, s);
@@ -670,6 +739,43 @@ bh_status bh_force_timing(bh_ctx *c, double *total_ms, int64_t *launches, int32_
     if (total_ms) *total_ms = tot;
     if (launches) *launches = (int64_t)c->force_ev_used;
     if (reset) c->force_ev_used = 0;
+    return BH_OK;
+}
+
+bh_status bh_autotune(bh_ctx *c, const int32_t *cand, int32_t n_cand, int32_t rebuild_every, int32_t *chosen,
+                      void *stream) {
+    if (!c) return BH_EINVAL;
+    if (!c->tree_valid) return fail(c, BH_ESTATE, "bh_autotune: no tree (call bh_build_tree first)");
+    if (!cand || n_cand < 1 || rebuild_every < 1) return fail(c, BH_EINVAL, "bh_autotune: bad candidates");
+    for (int k = 0; k < n_cand; ++k)
+        if (cand[k] < 1 || cand[k] > 65536) return fail(c, BH_EINVAL, "bh_autotune: bad group size");
+    hipStream_t s = (hipStream_t)stream;
+    double best = 1e300;
+    int best_g = cand[0];
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int k = 0; k < (pass == 0 ? n_cand : 1); ++k) {
+            c->n_grp_used = pass == 0 ? cand[k] : best_g;
+            refresh_state(c);
+            bhk::regroup(c->d, s);
+            bhk::make_groups(c->d, s);
+            STCHK(read_counters(c, s));
+            c->n_groups = c->h_cnt->n_groups;
+            STCHK(make_lists(c, s));
+            refresh_state(c);
+            STCHK(run_forces(c, s, false));
+            if (pass == 1) break;
+            double ms[EV_N];
+            STCHK(bh_stage_times(c, ms));
+            const double t = ms[EV_FORCE] + ms[EV_WALK] / rebuild_every;
+            if (t < best) {
+                best = t;
+                best_g = cand[k];
+            }
+        }
+    }
+    c->P.n_group = best_g;
+    c->state_valid = false;
+    if (chosen) *chosen = best_g;
     return BH_OK;
 }
 

@@ -181,6 +181,7 @@ void build_octree(const DevState &d, hipStream_t s);
 void moments(const DevState &d, hipStream_t s);
 void make_groups(const DevState &d, hipStream_t s);
 void reset_flags(const DevState &d, hipStream_t s);
+void regroup(const DevState &d, hipStream_t s);   // group flags for d.n_grp on the current tree
 
 // lists (bh_walk.hip)
 void walk(const DevState &d, hipStream_t s);

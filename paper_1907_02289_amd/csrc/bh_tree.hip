@@ -321,6 +321,30 @@ __global__ void k_moments_level(DevState d, int l) {
 }
 
 // ---------------------------------------------------------------- groups
+// Group flags for the current n_grp on an existing tree: a root is a group
+// when small enough or a leaf; a child is a group when its parent is larger
+// than n_grp and the child is small enough or a leaf (each node has exactly
+// one parent, so the writes do not collide).
+__global__ void k_regroup(DevState d) {
+    const uint32_t nn = d.cnt->lvl_off[BH_NLEVELS];
+    const uint32_t G = (uint32_t)d.n_grp;
+    uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nn; v += stride) {
+        const uint32_t meta = d.nd_meta[v], nch = meta_nch(meta), c = d.nd_count[v];
+        if (v < (uint32_t)d.n_sys) {
+            const bool grp = c <= G || nch == 0;
+            d.nd_meta[v] = make_meta(meta_level(meta), nch, grp ? 1u : 0u, meta_sys(meta));
+        }
+        const uint32_t f = d.nd_first[v];
+        for (uint32_t k = 0; k < nch; ++k) {
+            const uint32_t u = f + k;
+            const uint32_t mu = d.nd_meta[u];
+            const bool grp = c > G && (d.nd_count[u] <= G || meta_nch(mu) == 0);
+            d.nd_meta[u] = make_meta(meta_level(mu), meta_nch(mu), grp ? 1u : 0u, meta_sys(mu));
+        }
+    }
+}
+
 __global__ void k_group_mark(DevState d) {
     const uint32_t nn = d.cnt->lvl_off[BH_NLEVELS];
     uint32_t stride = gridDim.x * blockDim.x;
@@ -414,6 +438,10 @@ void build_octree(const DevState &d, hipStream_t s) {
 void moments(const DevState &d, hipStream_t s) {
     const unsigned g = grid_for(d.node_cap, 4096);
     for (int l = BH_MAXLEVEL; l >= 0; --l) k_moments_level<<<g, TPB, 0, s>>>(d, l);
+}
+
+void regroup(const DevState &d, hipStream_t s) {
+    k_regroup<<<grid_for(d.node_cap, 4096), TPB, 0, s>>>(d);
 }
 
 void make_groups(const DevState &d, hipStream_t s) {
