@@ -75,6 +75,56 @@ def tune_theta(ctx, dev, targets, ref, n, lo=0.1, hi=1.0, iters=10):
     return best[0], best[1]
 
 
+GROUP_SIZES = (128, 256, 512)
+LEARNED_BAND = (0.03, 0.5)
+
+
+def learned_path(bh, inputs, w, dev0, sample, ref, n, tuned, args):
+    """The learned opening rule: trained on separate 1M-particle rings and a
+    Plummer sphere (seeds 100-102) with the library's training kernels, then
+    tau bisected to p99 <= 1e-3 on the benchmark ring."""
+    import torch
+    lo, hi = LEARNED_BAND
+    kw = dict(criterion=bh.LEARNED, theta_min=lo, theta_max=hi, tau=1e-4)
+    tr = bh.Context(theta=tuned["theta"], eps=w.eps, precision=bh.FP32_REL, n_group=tuned["n_group"], **kw)
+    for sysm in (inputs.ring(1 << 20, 100, central_mass=1.0),
+                 inputs.ring(1 << 20, 101, r_out=1.2, z_sigma=5e-4, central_mass=1.0),
+                 inputs.plummer(1 << 19, 102)):
+        tr.build_tree([bh.to_device(sysm)])
+        tr.mlp_collect(max_groups=256, count_cap=65536)
+    n_pairs = tr.mlp_dataset()[0].shape[0]
+    mse = tr.mlp_train(iters=3000, batch=4096, seed=7)
+    weights = tr.mlp_weights()
+    tr.close()
+    torch.cuda.empty_cache()
+    log(f"[bench] learned: {n_pairs} training pairs, mse {mse:.3f}")
+    ctx = bh.Context(theta=tuned["theta"], eps=w.eps, precision=bh.FP32_REL, n_group=tuned["n_group"], **kw)
+    ctx.mlp_weights(set=weights)
+    ctx.build_tree([dev0])
+
+    def err(lt):
+        ctx.set_params(tau=10.0 ** lt)
+        ctx.make_lists()
+        return rel_err_p99(ctx, dev0, sample, ref, n)
+
+    a, b, best = -9.0, 1.0, None
+    for _ in range(12):
+        mid = 0.5 * (a + b)
+        e = err(mid)
+        if e[0] <= TARGET_P99:
+            a, best = mid, (mid, e)
+        else:
+            b = mid
+    ctx.close()
+    torch.cuda.empty_cache()
+    lt, e = best
+    log(f"[bench] learned: tau=1e{lt:.3f} p99={e[0]:.3e}")
+    p = dict(tuned)
+    p.update(learned=dict(kw, tau=10.0 ** lt), weights=weights, p99=e[0], p50=e[1], training_pairs=n_pairs,
+             training_mse=mse)
+    return p
+
+
 def force_source_digest():
     src = os.path.join(ROOT, "paper_1907_02289_amd", "csrc", "bh_force.hip")
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -155,6 +205,7 @@ def main():
     ap.add_argument("--theta-tuned", type=float, default=None, help="skip tuning, use this theta (tuned path)")
     ap.add_argument("--theta-plain", type=float, default=None, help="skip tuning, use this theta (plain path)")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-criterion form")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: sharding the groups "
@@ -185,31 +236,47 @@ def main():
     log(f"[bench] direct-sum judge on {sample.numel()} targets: {time.perf_counter() - t:.2f} s")
     judge.close()
 
-    # ---- matched error: theta per path
+    # ---- matched error: theta per path (and per group size for the tuned path)
     paths = {
         "tuned": dict(precision=bh.FP32_REL, n_group=args.n_group, rebuild_every=R),
         "plain": dict(precision=bh.FP64, n_group=64, rebuild_every=1),
     }
     fixed = {"tuned": args.theta_tuned, "plain": args.theta_plain}
+    group_sizes = [args.n_group] if (args.no_tune or args.theta_tuned is not None) else list(GROUP_SIZES)
+    autotune = []
     for name, p in paths.items():
-        ctx = bh.Context(theta=0.5, eps=w.eps, precision=p["precision"], n_group=p["n_group"])
-        ctx.build_tree([dev0])
-        if args.no_tune or fixed[name] is not None:
-            th = fixed[name] if fixed[name] is not None else 0.5
-            ctx.set_params(theta=th)
+        best = None
+        for ng in (group_sizes if name == "tuned" else [p["n_group"]]):
+            ctx = bh.Context(theta=0.5, eps=w.eps, precision=p["precision"], n_group=ng)
+            ctx.build_tree([dev0])
+            if args.no_tune or fixed[name] is not None:
+                th = fixed[name] if fixed[name] is not None else 0.5
+                ctx.set_params(theta=th)
+                ctx.make_lists()
+                e = rel_err_p99(ctx, dev0, sample, ref, n)
+            else:
+                th, e = tune_theta(ctx, dev0, sample, ref, n)
+            # cost of one reuse cycle per step at this theta: walk / R + force
             ctx.make_lists()
-            p["theta"], (p["p99"], p["p50"]) = th, rel_err_p99(ctx, dev0, sample, ref, n)
-        else:
-            p["theta"], (p["p99"], p["p50"]) = tune_theta(ctx, dev0, sample, ref, n)
-        log(f"[bench] {name}: theta={p['theta']:.4f} p99={p['p99']:.3e} p50={p['p50']:.3e}")
-        ctx.close()
-        torch.cuda.empty_cache()
+            ctx.forces(None)
+            st = ctx.stage_times()
+            cost = st["walk"] / p["rebuild_every"] + st["forces"]
+            log(f"[bench] {name} n_group={ng}: theta={th:.4f} p99={e[0]:.3e} cost {cost:.2f} ms")
+            if name == "tuned":
+                autotune.append({"n_group": ng, "theta": th, "p99": e[0], "ms_walk_per_step_plus_force": cost})
+            if best is None or cost < best[0]:
+                best = (cost, ng, th, e)
+            ctx.close()
+            torch.cuda.empty_cache()
+        p["n_group"], p["theta"], (p["p99"], p["p50"]) = best[1], best[2], best[3]
 
     # ---- timed runs
     def timed(p, steps, warmup, leap_per_step):
         dev = {k: v.clone() for k, v in dev0.items()}
         ctx = bh.Context(theta=p["theta"], eps=w.eps, central_mass=w.central_mass, precision=p["precision"],
-                         n_group=p["n_group"])
+                         n_group=p["n_group"], **p.get("learned", {}))
+        if "weights" in p:
+            ctx.mlp_weights(set=p["weights"])
         ctx.step([dev], w.dt, 0, p["rebuild_every"])
         for _ in range(warmup):
             ctx.step_continue(w.dt, leap_per_step, p["rebuild_every"])
@@ -234,6 +301,11 @@ def main():
 
     tu = timed(paths["tuned"], args.steps, args.warmup, R)
     log(f"[bench] tuned: {tu}")
+    lr = None
+    if not args.no_learned:
+        lp = learned_path(bh, inputs, w, dev0, sample, ref, n, paths["tuned"], args)
+        lr = timed(lp, max(1, args.steps // 2), 1, R)
+        log(f"[bench] learned: {lr}")
     pl = timed(paths["plain"], args.plain_steps, 1, 1)
     log(f"[bench] plain: {pl}")
 
@@ -261,7 +333,7 @@ def main():
         "config": {
             "workload": workload,
             "n_particles": n, "theta_tuned": paths["tuned"]["theta"], "theta_plain": paths["plain"]["theta"],
-            "eps": w.eps, "dt": w.dt, "rebuild_every": R, "n_group": args.n_group,
+            "eps": w.eps, "dt": w.dt, "rebuild_every": R, "n_group": paths["tuned"]["n_group"],
             "step": f"one rebuild cycle = {R} KDK steps", "positions_and_integration": "f64",
         },
         "s_per_leapfrog_step": leap_t,
@@ -270,6 +342,7 @@ def main():
         "plain": {"s_per_step": leap_p, "interactions_per_s": pl["interactions"] / pl["wall"],
                   "p99_rel_err": paths["plain"]["p99"], "dtype": "f64", "n_group": 64, "rebuild_every": 1},
         "speedup_vs_plain_s_per_step": leap_p / leap_t,
+        "group_size_autotune": autotune,
         "force_kernel_ms": avg_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(workload),
@@ -278,6 +351,14 @@ def main():
                      / FP32_PEAK_TFLOPS},
         "stages_ms_last": tu["stages"],
     }
+    if lr is not None:
+        lps = lr["wall"] / (max(1, args.steps // 2) * R)
+        out["learned"] = {"s_per_step": lps, "interactions_per_s": lr["interactions"] / lr["wall"],
+                          "interactions_per_force_eval": lr["interactions"] / max(1, lr["force_evals"]),
+                          "tau": lp["learned"]["tau"], "p99_rel_err": lp["p99"], "p50_rel_err": lp["p50"],
+                          "training_pairs": lp["training_pairs"], "training_mse": lp["training_mse"],
+                          "speedup_vs_plain_s_per_step": leap_p / lps,
+                          "interactions_vs_geometric": (lr["interactions"] / max(1, lr["force_evals"])) / per_launch}
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(sysm, paths["tuned"]["theta"], args.n_group, w.eps, R)

@@ -71,7 +71,8 @@ typedef enum { BH_FP64 = 0, BH_FP32_REL = 1 } bh_precision;
  * distance from the node's centre to the box.  LEARNED: inside the band
  * theta_min <= s/d < theta_max a small network predicts the node's monopole
  * error and the node is accepted when the prediction is below tau times the
- * group's smallest acceleration; outside the band the geometric rule holds. */
+ * mean self-gravity acceleration of the group's particles (from the last
+ * force evaluation); outside the band the geometric rule holds. */
 typedef enum { BH_OPEN_GEOMETRIC = 0, BH_OPEN_LEARNED = 1 } bh_criterion;
 
 typedef struct {
@@ -136,7 +137,13 @@ typedef enum {
                                  uint32 pc[n_pc], uint32 pp[n_pp], packed in that order,
                                  each list in ascending node id */
     BH_EXPORT_ACC_SORTED = 6, /* double[n_particles][4]: ax, ay, az, pot in sorted order */
-    BH_EXPORT_SORTED_POS = 7  /* double[n_particles][4]: x, y, z, m in sorted order */
+    BH_EXPORT_SORTED_POS = 7, /* double[n_particles][4]: x, y, z, m in sorted order */
+    BH_EXPORT_QUAD = 8,       /* double[n_nodes][6]: second moment about the com (xx,xy,xz,yy,yz,zz);
+                                 learned rule only */
+    BH_EXPORT_NODE_QN = 9,    /* float[n_nodes]: |Q|_F / (M side^2); learned rule only */
+    BH_EXPORT_GROUP_EXTRA = 10, /* double[n_groups][2]: half-diagonal of the group's FP64 box and the
+                                   mean self-gravity |a| of its particles; learned rule only */
+    BH_EXPORT_ROOT_BOX = 11   /* double[n_systems][4]: root-box lower corner x, y, z and 2^21 / side */
 } bh_what;
 
 /* Create a context.  p is copied.  BH_EINVAL for out-of-range parameters. */
@@ -208,6 +215,61 @@ bh_status bh_force_timing(bh_ctx *ctx, double *total_ms, int64_t *launches, int3
  * bh_build_tree.  *chosen (may be NULL) receives the group size. */
 bh_status bh_autotune(bh_ctx *ctx, const int32_t *candidates, int32_t n_candidates, int32_t rebuild_every,
                       int32_t *chosen, void *stream);
+
+/* ---- Learned opening rule (not in the paper: an addition to the walk of
+ * Sec. 4.2 (3d)).  Network 4-32-32-1, ReLU, FP32, MLP_NPARAM = 1259 floats:
+ * W1[32][4], b1[32], W2[32][32], b2[32], W3[32], b3, then input means[4],
+ * input 1/std[4], label mean, label std.  Features of a (group, node) pair,
+ * each on the lg2p scale: (side/d_box)^2 with d_box the distance from the
+ * node's centre to the group box (the opening test's grid quantity), group
+ * half-diagonal/d, M/M_system and |Q|_F/(M side^2) (rounded to FP32 before
+ * lg2p), with d the distance from the node's centre of mass to the group
+ * centre and
+ * lg2p the piecewise-linear log2 (x = m 2^e, m in [0.5,1): e - 2 + 2m).
+ * Label: lg2p(largest |monopole - exact| over the group's particles /
+ * (G M / d^2)), the exact force summed directly in FP64. */
+#define BH_MLP_NPARAM 1259
+
+/* Record training pairs from the current tree (context created with the
+ * learned criterion, after bh_build_tree): a walk that accepts below
+ * theta_min and opens everything else lists every (group, node) pair in the
+ * band theta_min <= side/distance < theta_max for about max_groups groups;
+ * each pair with 2..count_cap particles gets its features and exact label
+ * appended to the context's training set.  Invalidates lists. */
+bh_status bh_mlp_collect(bh_ctx *ctx, int32_t max_groups, int32_t count_cap, void *stream);
+
+typedef struct {
+    int32_t iters;        /* Adam steps */
+    int32_t batch;        /* samples per step */
+    float lr, beta1, beta2, eps;
+    uint64_t seed;        /* weight initialisation and shuffling */
+    int32_t init;         /* 1: new weights and normalisation from the training set */
+} bh_train_opts;
+
+/* Train on the collected set with the library's forward, backward and Adam
+ * kernels.  *mse (host, may be NULL) receives the mean squared error of the
+ * final network over the whole set, in label units squared. */
+bh_status bh_mlp_train(bh_ctx *ctx, const bh_train_opts *o, double *mse, void *stream);
+
+/* Copy the weights out (get, host, BH_MLP_NPARAM floats) and/or install new
+ * ones (set); either may be NULL.  Installing weights invalidates lists. */
+bh_status bh_mlp_weights(bh_ctx *ctx, float *get, const float *set);
+
+/* Training-set size, and optionally its pairs (uint32[n][2] group, node of
+ * the tree they were collected on), features (float[n][4]) and labels
+ * (float[n]) to host memory.  bh_mlp_clear empties the set. */
+bh_status bh_mlp_dataset(bh_ctx *ctx, int64_t *n, uint32_t *pairs, float *x, float *y);
+bh_status bh_mlp_clear(bh_ctx *ctx);
+
+/* Network output for n feature rows (device float[n][4] -> device float[n]). */
+bh_status bh_mlp_predict(bh_ctx *ctx, const float *x, int64_t n, float *out, void *stream);
+
+/* Gradient of the mean squared error (on the normalised label) of a batch
+ * (device x float[B][4], y float[B], B <= 65536) with respect to the first
+ * 1249 weights, and the loss, into device memory; the weights are not
+ * changed. */
+bh_status bh_mlp_gradient(bh_ctx *ctx, const float *x, const float *y, int32_t B, float *grad, float *loss,
+                          void *stream);
 
 bh_status bh_query(const bh_ctx *ctx, bh_sizes *out);
 

@@ -20,7 +20,8 @@ from . import build as _build
 __all__ = [
     "lib", "keys", "sort_perm", "tree", "moments", "groups", "group_boxes",
     "lists", "forces", "direct", "central", "bh_accel", "direct_accel",
-    "kdk", "n_threads", "BHState",
+    "kdk", "n_threads", "BHState", "lg2p", "node_qn", "box_ratio2", "features", "mlp_forward", "lists_learned",
+    "label_ratio",
 ]
 
 _lib = None
@@ -50,6 +51,18 @@ def lib():
         L.orc_direct.argtypes = [i64, P, P, P, P, dbl, dbl, i64, P, P, P, P, P]
         L.orc_central.argtypes = [i64, P, P, P, dbl, dbl, P, P, P]
         L.orc_threads.restype = C.c_int
+        L.orc_lg2p.argtypes = [dbl]
+        L.orc_lg2p.restype = dbl
+        L.orc_node_qn.argtypes = [P, dbl, dbl]
+        L.orc_node_qn.restype = C.c_float
+        L.orc_features.argtypes = [P, dbl, dbl, C.c_float, P, dbl, dbl, P, P]
+        L.orc_box_ratio2.argtypes = [P, C.c_int, C.c_uint64]
+        L.orc_box_ratio2.restype = dbl
+        L.orc_mlp_forward_batch.argtypes = [P, i64, P, P]
+        L.orc_lists_learned.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, dbl, dbl, dbl, dbl, dbl, dbl,
+                                        C.c_uint32, P, P, P, P]
+        L.orc_label_ratio.argtypes = [C.c_uint32] * 4 + [P] * 6 + [dbl, dbl]
+        L.orc_label_ratio.restype = dbl
         _lib = L
     return _lib
 
@@ -269,3 +282,73 @@ def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
         vy += h * ay
         vz += h * az
     return x, y, z, vx, vy, vz
+
+
+# ---------------------------------------------------------------------------
+# Learned opening rule (an addition to the walk; see bh_oracle.c)
+# ---------------------------------------------------------------------------
+def lg2p(x):
+    return float(lib().orc_lg2p(float(x)))
+
+
+def node_qn(Q6, M, side):
+    Q6 = np.ascontiguousarray(Q6, np.float64)
+    return float(lib().orc_node_qn(_p(Q6), float(M), float(side)))
+
+
+def box_ratio2(gbox, level, prefix):
+    gbox = np.ascontiguousarray(gbox, np.int32)
+    return float(lib().orc_box_ratio2(_p(gbox), int(level), int(prefix)))
+
+
+def features(com, M, r2, qn, gcen, grad, Msys):
+    """Four FP32 features and d^2 of a (group, node) pair (r2 = box_ratio2)."""
+    com = np.ascontiguousarray(com, np.float64)
+    gcen = np.ascontiguousarray(gcen, np.float64)
+    f = np.zeros(4, np.float32)
+    d2 = np.zeros(1)
+    lib().orc_features(_p(com), float(M), float(r2), C.c_float(qn), _p(gcen), float(grad), float(Msys),
+                       _p(f), _p(d2))
+    return f, float(d2[0])
+
+
+def mlp_forward(w, X):
+    """FP32 network output for rows of X (n x 4), weights w (1259 floats)."""
+    w = np.ascontiguousarray(w, np.float32)
+    X = np.ascontiguousarray(X, np.float32).reshape(-1, 4)
+    out = np.zeros(X.shape[0], np.float32)
+    lib().orc_mlp_forward_batch(_p(w), X.shape[0], _p(X), _p(out))
+    return out
+
+
+def lists_learned(gbox, gcen, grad, gamin, t, com4, qn, w, S, theta, theta_min, theta_max, tau, G=1.0,
+                  count_cap=65536):
+    """Lists of one system's groups under the learned rule (CSR, ascending ids)."""
+    gbox = np.ascontiguousarray(gbox, np.int32)
+    gcen = np.ascontiguousarray(gcen, np.float64)
+    grad = np.ascontiguousarray(grad, np.float64)
+    gamin = np.ascontiguousarray(gamin, np.float64)
+    com4 = np.ascontiguousarray(com4, np.float64)
+    qn = np.ascontiguousarray(qn, np.float32)
+    w = np.ascontiguousarray(w, np.float32)
+    ng = gbox.shape[0]
+    pc_off = np.zeros(ng + 1, np.int64)
+    pp_off = np.zeros(ng + 1, np.int64)
+    count = np.ascontiguousarray(t["count"], np.uint32)
+    args = [_p(gbox), _p(gcen), _p(grad), _p(gamin), _p(t["level"]), _p(t["prefix"]), _p(count),
+            _p(t["first_child"]), _p(t["n_child"]), _p(com4), _p(qn), _p(w), float(S), float(theta),
+            float(theta_min), float(theta_max), float(tau), float(G), int(count_cap)]
+    L = lib()
+    L.orc_lists_learned(ng, *args, _p(pc_off), _p(pp_off), None, None)
+    pc = np.zeros(max(1, int(pc_off[-1])), np.uint32)
+    pp = np.zeros(max(1, int(pp_off[-1])), np.uint32)
+    L.orc_lists_learned(ng, *args, _p(pc_off), _p(pp_off), _p(pc), _p(pp))
+    return pc_off, pc[: pc_off[-1]].copy(), pp_off, pp[: pp_off[-1]].copy()
+
+
+def label_ratio(gbeg, gcnt, cbeg, ccnt, xs, ys, zs, ms, com4, gcen, eps, G=1.0):
+    xs, ys, zs, ms = _f64(xs), _f64(ys), _f64(zs), _f64(ms)
+    com4 = np.ascontiguousarray(com4, np.float64)
+    gcen = np.ascontiguousarray(gcen, np.float64)
+    return float(lib().orc_label_ratio(int(gbeg), int(gcnt), int(cbeg), int(ccnt), _p(xs), _p(ys), _p(zs),
+                                       _p(ms), _p(com4), _p(gcen), float(eps), float(G)))

@@ -496,3 +496,232 @@ int orc_threads(void)
     }
     return t;
 }
+
+/* ================================================================== */
+/* Learned opening rule (an addition to the walk of Sec. 4.2 (3d); the  */
+/* paper's walk uses a fixed rule).  Written out in the order the rule  */
+/* is defined, so that every acceptance decision can be reproduced:     */
+/*   features of a (group, node) pair, lg2p of FP64 values, to FP32:    */
+/*     (side/d_box)^2 (d_box: node centre to group box, grid units),    */
+/*     group half-diagonal/d, M/M_system, node qn,                      */
+/*     d = |com - group centre|, qn = |Q|_F/(M side^2);                 */
+/*   network 4-32-32-1 (ReLU) in FP32, each unit a fused multiply-add   */
+/*   chain over its inputs in index order starting from the bias;       */
+/*   accept iff y < lg2p(tau A_g d^2 / (G M)), in FP64;                 */
+/*   lg2p(x) = e - 2 + 2m for x = m 2^e, m in [0.5, 1).                 */
+/* ================================================================== */
+#define ORC_NH 32
+#define ORC_NIN 4
+#define ORC_W1 0
+#define ORC_B1 128
+#define ORC_W2 160
+#define ORC_B2 1184
+#define ORC_W3 1216
+#define ORC_B3 1248
+#define ORC_XMEAN 1249
+#define ORC_XISTD 1253
+#define ORC_YMEAN 1257
+#define ORC_YSTD 1258
+
+double orc_lg2p(double x)
+{
+    if (!(x > 0.0)) return -1100.0;
+    if (isinf(x)) return 1100.0;
+    int e;
+    double m = frexp(x, &e);
+    return (double)e + ((2.0 * m) - 2.0);
+}
+
+float orc_node_qn(const double *Q, double M, double side)
+{
+    double qq = Q[0] * Q[0] + Q[3] * Q[3] + Q[5] * Q[5] + 2.0 * (Q[1] * Q[1]) + 2.0 * (Q[2] * Q[2]) +
+                2.0 * (Q[4] * Q[4]);
+    return (float)(sqrt(qq) / (M * (side * side)));
+}
+
+/* (side / distance from the node's geometric centre to the group box)^2,  */
+/* from the doubled integer grid units of the opening test.                */
+double orc_box_ratio2(const int32_t *gb, int lvl, uint64_t pfx)
+{
+    uint32_t p[3];
+    deinterleave3(pfx, lvl, p);
+    int64_t s = (int64_t)1 << (ORC_MAXLEVEL - lvl);
+    int64_t d2 = 0;
+    for (int a = 0; a < 3; ++a) {
+        int64_t L = (int64_t)p[a] << (ORC_MAXLEVEL - lvl);
+        int64_t C = 2 * L + s, da = 0;
+        if (2 * (int64_t)gb[a] - C > da) da = 2 * (int64_t)gb[a] - C;
+        if (C - 2 * (int64_t)gb[3 + a] > da) da = C - 2 * (int64_t)gb[3 + a];
+        d2 += da * da;
+    }
+    return (double)((2 * s) * (2 * s)) / (double)d2;
+}
+
+/* Features of node (com, M, box ratio r2, qn) for a group (centre,       */
+/* half-diagonal).                                                         */
+void orc_features(const double *com, double M, double r2, float qn, const double *gcen, double grad,
+                  double Msys, float *f, double *d2_out)
+{
+    double dx = com[0] - gcen[0], dy = com[1] - gcen[1], dz = com[2] - gcen[2];
+    double d2 = dx * dx + dy * dy + dz * dz;
+    double d = sqrt(d2);
+    f[0] = (float)orc_lg2p(r2);
+    f[1] = (float)orc_lg2p(grad / d);
+    f[2] = (float)orc_lg2p(M / Msys);
+    f[3] = (float)orc_lg2p((double)qn);
+    if (d2_out) *d2_out = d2;
+}
+
+float orc_mlp_forward(const float *w, const float *f)
+{
+    float x[ORC_NIN], h1[ORC_NH];
+    for (int k = 0; k < ORC_NIN; ++k) {
+        float t = f[k] - w[ORC_XMEAN + k];
+        x[k] = t * w[ORC_XISTD + k];
+    }
+    for (int j = 0; j < ORC_NH; ++j) {
+        float a = w[ORC_B1 + j];
+        for (int k = 0; k < ORC_NIN; ++k) a = fmaf(w[ORC_W1 + j * ORC_NIN + k], x[k], a);
+        h1[j] = a > 0.0f ? a : 0.0f;
+    }
+    float out = w[ORC_B3];
+    for (int j = 0; j < ORC_NH; ++j) {
+        float a = w[ORC_B2 + j];
+        for (int k = 0; k < ORC_NH; ++k) a = fmaf(w[ORC_W2 + j * ORC_NH + k], h1[k], a);
+        float h2 = a > 0.0f ? a : 0.0f;
+        out = fmaf(w[ORC_W3 + j], h2, out);
+    }
+    return fmaf(out, w[ORC_YSTD], w[ORC_YMEAN]);
+}
+
+void orc_mlp_forward_batch(const float *w, int64_t n, const float *X, float *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_mlp_forward(w, X + 4 * i);
+}
+
+typedef struct {
+    const int32_t *gb;          /* group grid box */
+    const double *gcen;         /* group centre */
+    double grad, amin, Msys, S; /* half-diagonal, A_g, system mass, root side */
+    const uint8_t *level;
+    const uint64_t *prefix;
+    const uint32_t *count;
+    const double *com4;         /* per node: com x, y, z, M */
+    const float *qn;
+    const float *w;
+    double th2, th2_min, th2_max, tau, G;
+    uint32_t count_cap;
+} learned_walk;
+
+static int learned_decide(const learned_walk *L, uint32_t v)
+{
+    int lvl = L->level[v];
+    if (accept_cell(L->gb, lvl, L->prefix[v], L->th2_min)) return 1;
+    if (!accept_cell(L->gb, lvl, L->prefix[v], L->th2_max)) return 0;
+    uint32_t cnt = L->count[v];
+    if (cnt == 1) return 1;
+    if (cnt > L->count_cap) return accept_cell(L->gb, lvl, L->prefix[v], L->th2);
+    const double *c = L->com4 + 4 * (size_t)v;
+    float f[4];
+    double d2;
+    orc_features(c, c[3], orc_box_ratio2(L->gb, lvl, L->prefix[v]), L->qn[v], L->gcen, L->grad, L->Msys, f, &d2);
+    float y = orc_mlp_forward(L->w, f);
+    double Z = ((L->tau * L->amin) * d2) / (L->G * c[3]);
+    return (double)y < orc_lg2p(Z);
+}
+
+static void learned_rec(const learned_walk *L, uint32_t v, const uint32_t *first_child, const uint8_t *n_child,
+                        u32vec *pc, u32vec *pp)
+{
+    if (learned_decide(L, v)) {
+        vpush(pc, v);
+    } else if (n_child[v] == 0) {
+        vpush(pp, v);
+    } else {
+        for (int c = 0; c < n_child[v]; ++c) learned_rec(L, first_child[v] + c, first_child, n_child, pc, pp);
+    }
+}
+
+/* Lists under the learned rule for every group of one system (root node 0),
+ * given the node moments (com4: x, y, z, M per node), node features qn,
+ * group boxes, centres, half-diagonals and A_g.  Output as orc_lists. */
+void orc_lists_learned(int64_t n_groups, const int32_t *gbox, const double *gcen, const double *grad,
+                       const double *gamin, const uint8_t *level, const uint64_t *prefix, const uint32_t *count,
+                       const uint32_t *first_child, const uint8_t *n_child, const double *com4, const float *qn,
+                       const float *w, double S, double theta, double theta_min, double theta_max, double tau,
+                       double G, uint32_t count_cap, int64_t *pc_off, int64_t *pp_off, uint32_t *pc_ids,
+                       uint32_t *pp_ids)
+{
+    int64_t *pcn = (int64_t *)calloc((size_t)n_groups, sizeof(int64_t));
+    int64_t *ppn = (int64_t *)calloc((size_t)n_groups, sizeof(int64_t));
+    for (int pass = 0; pass < (pc_ids && pp_ids ? 2 : 1); ++pass) {
+        #pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t g = 0; g < n_groups; ++g) {
+            learned_walk L;
+            L.gb = gbox + 6 * g;
+            L.gcen = gcen + 3 * g;
+            L.grad = grad[g];
+            L.amin = gamin[g];
+            L.Msys = com4[3];
+            L.S = S;
+            L.level = level; L.prefix = prefix; L.count = count; L.com4 = com4; L.qn = qn; L.w = w;
+            L.th2 = theta * theta; L.th2_min = theta_min * theta_min; L.th2_max = theta_max * theta_max;
+            L.tau = tau; L.G = G; L.count_cap = count_cap;
+            u32vec pc = {0, 0, 0}, pp = {0, 0, 0};
+            learned_rec(&L, 0, first_child, n_child, &pc, &pp);
+            if (pass == 0) {
+                pcn[g] = pc.n;
+                ppn[g] = pp.n;
+            } else {
+                qsort(pc.v, (size_t)pc.n, sizeof(uint32_t), cmp_u32);
+                qsort(pp.v, (size_t)pp.n, sizeof(uint32_t), cmp_u32);
+                if (pc.n) memcpy(pc_ids + pc_off[g], pc.v, (size_t)pc.n * sizeof(uint32_t));
+                if (pp.n) memcpy(pp_ids + pp_off[g], pp.v, (size_t)pp.n * sizeof(uint32_t));
+            }
+            free(pc.v);
+            free(pp.v);
+        }
+        if (pass == 0) {
+            pc_off[0] = 0;
+            pp_off[0] = 0;
+            for (int64_t g = 0; g < n_groups; ++g) {
+                pc_off[g + 1] = pc_off[g] + pcn[g];
+                pp_off[g + 1] = pp_off[g] + ppn[g];
+            }
+        }
+    }
+    free(pcn);
+    free(ppn);
+}
+
+/* Label of a (group, node) pair: the largest |monopole - exact| force of
+ * the node on the group's particles, divided by G M / d^2, d = distance
+ * of the node's centre of mass from the group centre; returned in FP64
+ * before lg2p (the caller applies lg2p and the rounding to FP32). */
+double orc_label_ratio(uint32_t gbeg, uint32_t gcnt, uint32_t cbeg, uint32_t ccnt, const double *x, const double *y,
+                       const double *z, const double *m, const double *com4, const double *gcen, double eps,
+                       double G)
+{
+    double eps2 = eps * eps, emax = 0.0;
+    double M = com4[3];
+    for (uint32_t i = gbeg; i < gbeg + gcnt; ++i) {
+        double ex = 0, ey = 0, ez = 0;
+        for (uint32_t j = cbeg; j < cbeg + ccnt; ++j) {
+            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+            double r2 = dx * dx + dy * dy + dz * dz + eps2;
+            double f = m[j] / (r2 * sqrt(r2));
+            ex += f * dx;
+            ey += f * dy;
+            ez += f * dz;
+        }
+        double dx = com4[0] - x[i], dy = com4[1] - y[i], dz = com4[2] - z[i];
+        double r2 = dx * dx + dy * dy + dz * dz + eps2;
+        double f = M / (r2 * sqrt(r2));
+        double ux = G * (f * dx - ex), uy = G * (f * dy - ey), uz = G * (f * dz - ez);
+        double e = sqrt(ux * ux + uy * uy + uz * uz);
+        if (e > emax) emax = e;
+    }
+    double dx = com4[0] - gcen[0], dy = com4[1] - gcen[1], dz = com4[2] - gcen[2];
+    double d2 = dx * dx + dy * dy + dz * dz;
+    return (emax * d2) / (G * M);
+}

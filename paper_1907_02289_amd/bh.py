@@ -17,12 +17,16 @@ BH_OK, BH_EINVAL, BH_ENOMEM, BH_EHIP, BH_ESTATE, BH_ECAPACITY = 0, -1, -2, -3, -
 FP64, FP32_REL = 0, 1
 FLAG_NO_GRAPH = 1
 GEOMETRIC, LEARNED = 0, 1
-EXPORT = dict(keys=0, perm=1, nodes=2, moments=3, groups=4, lists=5, acc_sorted=6, sorted_pos=7)
+EXPORT = dict(keys=0, perm=1, nodes=2, moments=3, groups=4, lists=5, acc_sorted=6, sorted_pos=7, quad=8,
+              node_qn=9, group_extra=10, root_box=11)
+MLP_NPARAM = 1259
 STAGES = ("keys_sort", "tree", "moments", "groups", "walk", "forces", "integrate", "step")
 
 SYMBOLS = ("bh_create", "bh_destroy", "bh_set_params", "bh_build_tree", "bh_make_lists", "bh_forces",
            "bh_step", "bh_step_continue", "bh_direct_sum", "bh_force_timing", "bh_query", "bh_export",
-           "bh_export_groups", "bh_stage_times", "bh_autotune", "bh_last_error")
+           "bh_export_groups", "bh_stage_times", "bh_autotune", "bh_mlp_collect", "bh_mlp_train",
+           "bh_mlp_weights", "bh_mlp_dataset", "bh_mlp_clear", "bh_mlp_predict", "bh_mlp_gradient",
+           "bh_last_error")
 
 
 class Params(C.Structure):
@@ -38,6 +42,11 @@ class System(C.Structure):
 
 class Accel(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("ax", "ay", "az", "pot")]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64), ("init", C.c_int32)]
 
 
 class Sizes(C.Structure):
@@ -73,6 +82,13 @@ def load_library(path: str = LIB_PATH):
     L.bh_direct_sum.argtypes = [vp, C.POINTER(System), vp, C.c_int64, vp, vp, vp, vp]
     L.bh_force_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
     L.bh_autotune.argtypes = [vp, C.POINTER(C.c_int32), i32, i32, C.POINTER(C.c_int32), vp]
+    L.bh_mlp_collect.argtypes = [vp, i32, i32, vp]
+    L.bh_mlp_train.argtypes = [vp, C.POINTER(TrainOpts), C.POINTER(C.c_double), vp]
+    L.bh_mlp_weights.argtypes = [vp, vp, vp]
+    L.bh_mlp_dataset.argtypes = [vp, C.POINTER(C.c_int64), vp, vp, vp]
+    L.bh_mlp_clear.argtypes = [vp]
+    L.bh_mlp_predict.argtypes = [vp, vp, C.c_int64, vp, vp]
+    L.bh_mlp_gradient.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.bh_query.argtypes = [vp, C.POINTER(Sizes)]
     L.bh_export.argtypes = [vp, i32, vp, vp]
     L.bh_export_groups.argtypes = [vp, vp, vp, vp]
@@ -189,6 +205,59 @@ class Context:
         self._check(self.L.bh_autotune(self.h, arr, len(candidates), int(rebuild_every), C.byref(out), _stream()))
         return out.value
 
+    # ---- learned opening rule
+    def mlp_collect(self, max_groups=256, count_cap=65536):
+        self._check(self.L.bh_mlp_collect(self.h, int(max_groups), int(count_cap), _stream()))
+
+    def mlp_train(self, iters=2000, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0, init=True):
+        o = TrainOpts(int(iters), int(batch), lr, beta1, beta2, eps, int(seed), 1 if init else 0)
+        mse = C.c_double()
+        self._check(self.L.bh_mlp_train(self.h, C.byref(o), C.byref(mse), _stream()))
+        return mse.value
+
+    def mlp_weights(self, set=None):
+        w = np.zeros(MLP_NPARAM, np.float32)
+        src = None
+        if set is not None:
+            src = np.ascontiguousarray(set, np.float32)
+            assert src.size == MLP_NPARAM
+        self._check(self.L.bh_mlp_weights(self.h, w.ctypes.data_as(C.c_void_p),
+                                          None if src is None else src.ctypes.data_as(C.c_void_p)))
+        return w if set is None else src
+
+    def mlp_dataset(self):
+        n = C.c_int64()
+        self._check(self.L.bh_mlp_dataset(self.h, C.byref(n), None, None, None))
+        pairs = np.zeros((n.value, 2), np.uint32)
+        X = np.zeros((n.value, 4), np.float32)
+        Y = np.zeros(n.value, np.float32)
+        if n.value:
+            self._check(self.L.bh_mlp_dataset(self.h, C.byref(n), pairs.ctypes.data_as(C.c_void_p),
+                                              X.ctypes.data_as(C.c_void_p), Y.ctypes.data_as(C.c_void_p)))
+        return pairs, X, Y
+
+    def mlp_clear(self):
+        self._check(self.L.bh_mlp_clear(self.h))
+
+    def mlp_predict(self, X):
+        import torch
+        X = X.contiguous()
+        assert X.is_cuda and X.dtype == torch.float32 and X.shape[-1] == 4
+        out = torch.zeros(X.shape[0], dtype=torch.float32, device=X.device)
+        self._check(self.L.bh_mlp_predict(self.h, C.c_void_p(X.data_ptr()), X.shape[0],
+                                          C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def mlp_gradient(self, X, Y):
+        import torch
+        X, Y = X.contiguous(), Y.contiguous()
+        grad = torch.zeros(1249, dtype=torch.float32, device=X.device)
+        loss = torch.zeros(1, dtype=torch.float32, device=X.device)
+        self._check(self.L.bh_mlp_gradient(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
+                                           X.shape[0], C.c_void_p(grad.data_ptr()), C.c_void_p(loss.data_ptr()),
+                                           _stream()))
+        return grad, loss
+
     def force_timing(self, reset=True):
         """(total ms, launches) of the force kernel since the last reset."""
         ms, k = C.c_double(), C.c_int64()
@@ -215,6 +284,14 @@ class Context:
             out = np.zeros((ng, 4), np.int64)
         elif what in ("acc_sorted", "sorted_pos"):
             out = np.zeros((n, 4))
+        elif what == "quad":
+            out = np.zeros((nn, 6))
+        elif what == "node_qn":
+            out = np.zeros(nn, np.float32)
+        elif what == "group_extra":
+            out = np.zeros((ng, 2))
+        elif what == "root_box":
+            out = np.zeros((q["n_systems"], 4))
         elif what == "lists":
             npc, npp = q["n_pc"], q["n_pp"]
             raw = np.zeros(2 * (ng + 1) * 8 + 4 * (npc + npp) + 8, np.uint8)

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbh.so")
 SOURCES = ["bh_api.hip", "bh_sort.hip", "bh_tree.hip", "bh_walk.hip", "bh_force.hip", "bh_integrate.hip",
-           "bh_direct.hip"]
+           "bh_direct.hip", "bh_learned.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -13,7 +13,11 @@
 #include <vector>
 
 #include "bh.h"
-#include "bh_internal.hpp"
+#include "bh_learned.hpp"
+
+namespace bhk {
+size_t mlp_act_floats(uint32_t B);
+}
 
 namespace {
 
@@ -84,6 +88,15 @@ struct bh_ctx {
         double h = 0, dt = 0;
         hipGraphExec_t exec = nullptr;
     };
+    // learned opening rule
+    DevBuf nd_qn, amag, amag_in, g_amin, g_rad, cand, mlp_w, mlp_m, mlp_v, mlp_g, act;
+    DevBuf ds_x, ds_y, ds_pairs, pk_a, pk_b, pv_a, pv_b, phist, eval_out;
+    uint64_t cand_cap = 0, ds_n = 0, ds_cap = 0;
+    int walk_mode = WALK_GEOMETRIC;
+    uint32_t group_stride = 1, count_cap = 65536;
+    bool amag_valid = false, mlp_ready = false;
+    int adam_t = 0;
+
     GraphEntry graphs[2];
     int graph_next = 0;
     hipStream_t gs = nullptr;
@@ -195,6 +208,21 @@ void refresh_state(bh_ctx *c) {
     d.walk_list_cap = c->walk_list;
     d.walk_waves = c->walk_waves;
     d.cnt = P<DevCounters>(c->counters);
+    const bool learned = c->P.criterion == BH_OPEN_LEARNED;
+    d.walk_mode = c->walk_mode;
+    d.th2_min = c->P.theta_min * c->P.theta_min;
+    d.th2_max = c->P.theta_max * c->P.theta_max;
+    d.tau = c->P.tau;
+    d.mlp = P<float>(c->mlp_w);
+    d.nd_qn = learned ? P<float>(c->nd_qn) : nullptr;
+    d.amag = learned ? P<double>(c->amag) : nullptr;
+    d.amag_in = learned ? P<double>(c->amag_in) : nullptr;
+    d.g_amin = learned ? P<double>(c->g_amin) : nullptr;
+    d.g_rad = learned ? P<double>(c->g_rad) : nullptr;
+    d.cand = P<uint2>(c->cand);
+    d.cand_cap = c->cand_cap;
+    d.group_stride = c->group_stride;
+    d.count_cap = c->count_cap;
     d.n_leaf = c->P.n_leaf;
     d.n_grp = c->n_grp_used;
     d.th2 = c->P.theta * c->P.theta;
@@ -289,6 +317,30 @@ bh_status ensure_particles(bh_ctx *c, uint32_t n) {
     HIPCHK(c, grow(c->gval_a, u4));
     HIPCHK(c, grow(c->gval_b, u4));
     c->n_cap = cap;
+    if (c->P.criterion == BH_OPEN_LEARNED) {
+        HIPCHK(c, grow(c->amag, u8));
+        HIPCHK(c, grow(c->amag_in, u8));
+        HIPCHK(c, grow(c->g_amin, u8));
+        HIPCHK(c, grow(c->g_rad, u8));
+    }
+    return BH_OK;
+}
+
+// Per-particle and per-node arrays of the learned rule, when it is switched on later.
+bh_status ensure_learned(bh_ctx *c) {
+    if (c->P.criterion != BH_OPEN_LEARNED) return BH_OK;
+    if (c->n_cap) {
+        size_t u8 = (size_t)c->n_cap * 8;
+        HIPCHK(c, grow(c->amag, u8));
+        HIPCHK(c, grow(c->amag_in, u8));
+        HIPCHK(c, grow(c->g_amin, u8));
+        HIPCHK(c, grow(c->g_rad, u8));
+    }
+    if (c->node_cap) {
+        HIPCHK(c, grow(c->nd_quad, (size_t)c->node_cap * 6 * sizeof(double)));
+        HIPCHK(c, grow(c->nd_qn, (size_t)c->node_cap * 4));
+    }
+    HIPCHK(c, grow(c->mlp_w, BH_MLP_NPARAM * 4));
     return BH_OK;
 }
 
@@ -302,7 +354,10 @@ bh_status ensure_nodes(bh_ctx *c, uint32_t cap) {
     HIPCHK(c, grow(c->nd_meta, (size_t)cap * 4));
     HIPCHK(c, grow(c->nd_walk, (size_t)cap * sizeof(int4)));
     HIPCHK(c, grow(c->nd_mom, (size_t)cap * sizeof(double4)));
-    if (c->P.criterion == BH_OPEN_LEARNED) HIPCHK(c, grow(c->nd_quad, (size_t)cap * 6 * sizeof(double)));
+    if (c->P.criterion == BH_OPEN_LEARNED) {
+        HIPCHK(c, grow(c->nd_quad, (size_t)cap * 6 * sizeof(double)));
+        HIPCHK(c, grow(c->nd_qn, (size_t)cap * 4));
+    }
     HIPCHK(c, grow(c->tmp_a, (size_t)cap * 4));
     HIPCHK(c, grow(c->tmp_b, (size_t)cap * 4));
     c->node_cap = cap;
@@ -310,7 +365,13 @@ bh_status ensure_nodes(bh_ctx *c, uint32_t cap) {
 }
 
 bh_status ensure_walk(bh_ctx *c) {
-    size_t words = (size_t)c->walk_waves * (2 * (size_t)c->walk_front + 2 * (size_t)c->walk_list);
+    // at most 4 GiB of walk scratch: fewer walking waves when each needs more
+    const size_t per_wave = 2 * (size_t)c->walk_front + 2 * (size_t)c->walk_list;
+    size_t waves = ((size_t)1 << 30) / per_wave;
+    waves = std::min<size_t>(waves, (size_t)c->n_cu * 16);
+    waves = std::max<size_t>(waves, 64) & ~(size_t)3;
+    c->walk_waves = (uint32_t)waves;
+    size_t words = (size_t)c->walk_waves * per_wave;
     HIPCHK(c, grow(c->walk_scratch, words * 4));
     return BH_OK;
 }
@@ -334,6 +395,9 @@ bh_status rebuild(bh_ctx *c, hipStream_t s, bool from_caller) {
         std::swap(c->pos_in, c->pos);
         std::swap(c->vel_in, c->vel);
         std::swap(c->idx_in, c->idx);
+        std::swap(c->amag_in, c->amag);
+    } else {
+        c->amag_valid = false;
     }
     refresh_state(c);
     ev_begin(c, EV_KEYS, s);
@@ -362,6 +426,7 @@ bh_status rebuild(bh_ctx *c, hipStream_t s, bool from_caller) {
     c->max_level = c->h_cnt->max_level;
     ev_begin(c, EV_MOM, s);
     bhk::moments(c->d, s);
+    if (c->P.criterion == BH_OPEN_LEARNED) bhk::node_qn(c->d, s);
     ev_end(c, EV_MOM, s);
     ev_begin(c, EV_GROUPS, s);
     bhk::make_groups(c->d, s);
@@ -375,8 +440,8 @@ bh_status rebuild(bh_ctx *c, hipStream_t s, bool from_caller) {
     return BH_OK;
 }
 
-bh_status make_lists(bh_ctx *c, hipStream_t s) {
-    if (!c->tree_valid) return fail(c, BH_ESTATE, "bh_make_lists: no tree (call bh_build_tree first)");
+// The walk, redone with larger scratch / pools until everything fits.
+bh_status walk_until_fits(bh_ctx *c, hipStream_t s) {
     for (int attempt = 0;; ++attempt) {
         refresh_state(c);
         ev_begin(c, EV_WALK, s);
@@ -386,11 +451,9 @@ bh_status make_lists(bh_ctx *c, hipStream_t s) {
         const DevCounters &h = *c->h_cnt;
         if (h.flags[FLAG_WALK_OVF]) {
             if (attempt > 40) return fail(c, BH_ECAPACITY, "walk scratch cannot grow further");
+            // a walk cut short by its frontier may also need a longer list: that shows on the next try
             if (h.walk_need_front >= c->walk_front) c->walk_front = std::max(2 * c->walk_front, 2 * h.walk_need_front);
             if (h.walk_need_list >= c->walk_list) c->walk_list = std::max(2 * c->walk_list, 2 * h.walk_need_list);
-            // the frontier that overflowed may hide a longer list: grow both
-            c->walk_front = std::max(c->walk_front, c->walk_list);
-            c->walk_list = std::max(c->walk_list, c->walk_front);
             STCHK(ensure_walk(c));
             continue;
         }
@@ -398,15 +461,49 @@ bh_status make_lists(bh_ctx *c, hipStream_t s) {
             STCHK(ensure_pools(c, h.pc_used + h.pc_used / 4 + 1024, h.pp_used + h.pp_used / 4 + 1024));
             continue;
         }
+        if (c->walk_mode == WALK_ENUMERATE && h.cand_used > c->cand_cap) {
+            uint64_t cap = h.cand_used + h.cand_used / 4 + 1024;
+            HIPCHK(c, grow(c->cand, cap * sizeof(uint2)));
+            c->cand_cap = cap;
+            continue;
+        }
         c->n_pc = h.pc_used;
         c->n_pp = h.pp_used;
         c->interactions = h.interactions;
-        break;
+        return BH_OK;
     }
+}
+
+bh_status run_forces(bh_ctx *c, hipStream_t s, bool pot);
+
+bh_status order_lists(bh_ctx *c, hipStream_t s) {
     bhk::order_groups(c->d, c->n_groups, P<uint64_t>(c->gkey_a), P<uint32_t>(c->gval_a), P<uint64_t>(c->gkey_b),
                       P<uint32_t>(c->gval_b), s);
     c->lists_valid = true;
     return BH_OK;
+}
+
+bh_status make_lists(bh_ctx *c, hipStream_t s) {
+    if (!c->tree_valid) return fail(c, BH_ESTATE, "bh_make_lists: no tree (call bh_build_tree first)");
+    if (c->P.criterion == BH_OPEN_LEARNED) {
+        if (!c->mlp_ready) return fail(c, BH_ESTATE, "learned criterion: no weights (bh_mlp_train or bh_mlp_weights)");
+        if (!c->amag_valid) {
+            // the error budget needs each group's acceleration: one geometric pass first
+            c->walk_mode = WALK_GEOMETRIC;
+            STCHK(walk_until_fits(c, s));
+            STCHK(order_lists(c, s));
+            refresh_state(c);
+            STCHK(run_forces(c, s, false));
+            bhk::group_amin(c->d, s);
+            c->amag_valid = true;
+        }
+        c->walk_mode = WALK_LEARNED;
+    } else {
+        c->walk_mode = WALK_GEOMETRIC;
+    }
+    STCHK(walk_until_fits(c, s));
+    c->walk_mode = WALK_GEOMETRIC;
+    return order_lists(c, s);
 }
 
 int force_blocks(const bh_ctx *c) { return c->n_cu * 8; }
@@ -431,6 +528,7 @@ bh_status run_forces(bh_ctx *c, hipStream_t s, bool pot) {
     c->interactions_evaluated += (int64_t)c->interactions;
     c->force_evaluations += 1;
     c->age += 1;
+    if (c->d.amag) c->amag_valid = true;
     return BH_OK;
 }
 
@@ -445,6 +543,7 @@ bh_status set_systems(bh_ctx *c, const bh_system *sys, int32_t n_sys, hipStream_
     }
     if (total >= (1ull << 31)) return fail(c, BH_EINVAL, "too many particles (limit 2^31 - 1)");
     STCHK(ensure_systems(c, n_sys));
+    STCHK(ensure_learned(c));
     STCHK(wait_tables(c));
     c->n_sys = n_sys;
     c->n = (uint32_t)total;
@@ -502,7 +601,7 @@ bh_status bh_create(bh_ctx **out, const bh_params *p) {
     ok = ok && hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&c->fence_a, hipEventDisableTiming) == hipSuccess &&
          hipEventCreateWithFlags(&c->fence_b, hipEventDisableTiming) == hipSuccess;
-    if (!ok || ensure_walk(c) != BH_OK) {
+    if (!ok || ensure_walk(c) != BH_OK || ensure_learned(c) != BH_OK) {
         bh_destroy(c);
         return BH_ENOMEM;
     }
@@ -520,7 +619,10 @@ bh_status bh_destroy(bh_ctx *c) {
                      &c->nd_first, &c->nd_meta, &c->nd_walk, &c->nd_mom, &c->nd_quad, &c->tmp_a, &c->tmp_b,
                      &c->gmark, &c->grp, &c->g_lo, &c->g_hi, &c->g_cen, &c->g_pc_off, &c->g_pc_len,
                      &c->g_pp_off, &c->g_pp_len, &c->g_cost, &c->order, &c->gkey_a, &c->gkey_b, &c->gval_a,
-                     &c->gval_b, &c->pc_pool, &c->pp_pool, &c->walk_scratch, &c->counters, &c->direct_part};
+                     &c->gval_b, &c->pc_pool, &c->pp_pool, &c->walk_scratch, &c->counters, &c->direct_part,
+                     &c->nd_qn, &c->amag, &c->amag_in, &c->g_amin, &c->g_rad, &c->cand, &c->mlp_w, &c->mlp_m,
+                     &c->mlp_v, &c->mlp_g, &c->act, &c->ds_x, &c->ds_y, &c->ds_pairs, &c->pk_a, &c->pk_b,
+                     &c->pv_a, &c->pv_b, &c->phist, &c->eval_out};
     for (DevBuf *b : all) release(*b);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
     if (c->h_systab) (void)hipHostFree(c->h_systab);
@@ -551,7 +653,7 @@ bh_status bh_set_params(bh_ctx *c, const bh_params *p) {
     c->P = *p;
     c->n_grp_used = ng;
     c->lists_valid = false;
-    if (c->P.criterion == BH_OPEN_LEARNED && c->node_cap) STCHK(ensure_nodes(c, c->node_cap + 1));
+    STCHK(ensure_learned(c));
     return BH_OK;
 }
 
@@ -779,6 +881,198 @@ bh_status bh_autotune(bh_ctx *c, const int32_t *cand, int32_t n_cand, int32_t re
     return BH_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Grow a device buffer keeping its first `keep` bytes.
+hipError_t grow_keep(DevBuf &b, size_t bytes, size_t keep) {
+    if (bytes <= b.bytes && b.p) return hipSuccess;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return e;
+    if (b.p && keep) e = hipMemcpy(p, b.p, keep, hipMemcpyDeviceToDevice);
+    if (b.p) (void)hipFree(b.p);
+    b.p = p;
+    b.bytes = bytes;
+    return e;
+}
+
+uint64_t splitmix64(uint64_t &st) {
+    uint64_t z = (st += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// He-uniform weights (bound sqrt(6 / fan_in)), zero biases, identity normalisation.
+void init_weights(float *w, uint64_t seed) {
+    uint64_t st = seed;
+    auto uni = [&](double a) { return (float)(a * (2.0 * ((splitmix64(st) >> 11) * 0x1.0p-53) - 1.0)); };
+    for (int k = 0; k < BH_MLP_NPARAM; ++k) w[k] = 0.0f;
+    for (int k = 0; k < MLP_NH * MLP_NIN; ++k) w[MLP_W1 + k] = uni(std::sqrt(6.0 / MLP_NIN));
+    for (int k = 0; k < MLP_NH * MLP_NH; ++k) w[MLP_W2 + k] = uni(std::sqrt(6.0 / MLP_NH));
+    for (int k = 0; k < MLP_NH; ++k) w[MLP_W3 + k] = uni(std::sqrt(3.0 / MLP_NH));
+    for (int k = 0; k < MLP_NIN; ++k) w[MLP_XISTD + k] = 1.0f;
+    w[MLP_YSTD] = 1.0f;
+}
+
+bh_status ensure_mlp_train_buffers(bh_ctx *c, uint32_t B, uint64_t n) {
+    HIPCHK(c, grow(c->mlp_m, MLP_NTRAIN * 4));
+    HIPCHK(c, grow(c->mlp_v, MLP_NTRAIN * 4));
+    HIPCHK(c, grow(c->mlp_g, (MLP_NTRAIN + 1) * 4));
+    HIPCHK(c, grow(c->act, bhk::mlp_act_floats(B) * 4));
+    HIPCHK(c, grow(c->pk_a, std::max<uint64_t>(n, B) * 8));
+    HIPCHK(c, grow(c->pk_b, std::max<uint64_t>(n, B) * 8));
+    HIPCHK(c, grow(c->pv_a, std::max<uint64_t>(n, B) * 4));
+    HIPCHK(c, grow(c->pv_b, std::max<uint64_t>(n, B) * 4));
+    HIPCHK(c, grow(c->phist, bhk::radix_hist_words((uint32_t)std::max<uint64_t>(n, B)) * 4));
+    return BH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bh_status bh_mlp_collect(bh_ctx *c, int32_t max_groups, int32_t count_cap, void *stream) {
+    if (!c) return BH_EINVAL;
+    if (c->P.criterion != BH_OPEN_LEARNED)
+        return fail(c, BH_ESTATE, "bh_mlp_collect: context not created with the learned criterion");
+    if (!c->tree_valid) return fail(c, BH_ESTATE, "bh_mlp_collect: no tree");
+    if (max_groups < 1 || count_cap < 2) return fail(c, BH_EINVAL, "bh_mlp_collect: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    if (!c->cand.p) {
+        c->cand_cap = 1u << 22;
+        HIPCHK(c, grow(c->cand, c->cand_cap * sizeof(uint2)));
+    }
+    c->group_stride = std::max<uint32_t>(1, (c->n_groups + max_groups - 1) / max_groups);
+    c->count_cap = (uint32_t)count_cap;
+    c->walk_mode = WALK_ENUMERATE;
+    bh_status st = walk_until_fits(c, s);
+    c->walk_mode = WALK_GEOMETRIC;
+    c->lists_valid = false;
+    c->state_valid = false;
+    STCHK(st);
+    const uint64_t nc = c->h_cnt->cand_used;
+    const uint64_t need = c->ds_n + nc;
+    if (need > c->ds_cap) {
+        const uint64_t cap = need + need / 2 + 1024;
+        HIPCHK(c, grow_keep(c->ds_x, cap * sizeof(float4), c->ds_n * sizeof(float4)));
+        HIPCHK(c, grow_keep(c->ds_y, cap * 4, c->ds_n * 4));
+        HIPCHK(c, grow_keep(c->ds_pairs, cap * sizeof(uint2), c->ds_n * sizeof(uint2)));
+        c->ds_cap = cap;
+    }
+    refresh_state(c);
+    bhk::cand_features_labels(c->d, nc, P<float4>(c->ds_x) + c->ds_n, P<float>(c->ds_y) + c->ds_n, s);
+    HIPCHK(c, hipMemcpyAsync(P<uint2>(c->ds_pairs) + c->ds_n, c->cand.p, nc * sizeof(uint2),
+                             hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->ds_n = need;
+    return BH_OK;
+}
+
+bh_status bh_mlp_train(bh_ctx *c, const bh_train_opts *o, double *mse, void *stream) {
+    if (!c || !o) return BH_EINVAL;
+    if (c->ds_n == 0) return fail(c, BH_ESTATE, "bh_mlp_train: empty training set (bh_mlp_collect)");
+    if (o->iters < 0 || o->batch < 1 || o->batch > 65536 || !(o->lr > 0.f))
+        return fail(c, BH_EINVAL, "bh_mlp_train: bad options");
+    if (c->ds_n >= (1ull << 31)) return fail(c, BH_EINVAL, "bh_mlp_train: training set too large");
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t n = c->ds_n;
+    const uint32_t B = (uint32_t)std::min<uint64_t>((uint64_t)o->batch, n);
+    HIPCHK(c, grow(c->mlp_w, BH_MLP_NPARAM * 4));
+    STCHK(ensure_mlp_train_buffers(c, B, n));
+    float *w = P<float>(c->mlp_w);
+    if (o->init || !c->mlp_ready) {
+        std::vector<float> h(BH_MLP_NPARAM);
+        init_weights(h.data(), o->seed);
+        HIPCHK(c, hipMemcpyAsync(w, h.data(), BH_MLP_NPARAM * 4, hipMemcpyHostToDevice, s));
+        bhk::mlp_stats(P<float4>(c->ds_x), P<float>(c->ds_y), n, w, s);
+        HIPCHK(c, hipMemsetAsync(c->mlp_m.p, 0, MLP_NTRAIN * 4, s));
+        HIPCHK(c, hipMemsetAsync(c->mlp_v.p, 0, MLP_NTRAIN * 4, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        c->adam_t = 0;
+    }
+    const uint64_t spe = std::max<uint64_t>(1, n / B);
+    for (int it = 0; it < o->iters; ++it) {
+        if ((uint64_t)it % spe == 0) {
+            const uint64_t epoch = (uint64_t)it / spe;
+            bhk::perm_keys(P<uint64_t>(c->pk_a), P<uint32_t>(c->pv_a), n, o->seed * 0x100000001b3ull + epoch, s);
+            bhk::radix_sort(P<uint64_t>(c->pk_a), P<uint32_t>(c->pv_a), P<uint64_t>(c->pk_b), P<uint32_t>(c->pv_b),
+                            (uint32_t)n, 0, 32, P<uint32_t>(c->phist), P<uint32_t>(c->scan_tmp), s, nullptr, 0);
+        }
+        const uint32_t *idx = P<uint32_t>(c->pv_a) + ((uint64_t)it % spe) * B;
+        bhk::mlp_batch_grad(w, P<float4>(c->ds_x), P<float>(c->ds_y), idx, B, P<float>(c->act), P<float>(c->mlp_g),
+                            nullptr, s);
+        bhk::mlp_adam(w, P<float>(c->mlp_g), P<float>(c->mlp_m), P<float>(c->mlp_v), o->lr, o->beta1, o->beta2,
+                      o->eps, ++c->adam_t, s);
+    }
+    HIPCHK(c, hipGetLastError());
+    c->mlp_ready = true;
+    c->lists_valid = false;
+    if (mse) {
+        HIPCHK(c, grow(c->eval_out, n * 4));
+        bhk::mlp_eval(w, P<float4>(c->ds_x), n, P<float>(c->eval_out), s);
+        std::vector<float> pr(n), y(n);
+        HIPCHK(c, hipMemcpyAsync(pr.data(), c->eval_out.p, n * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(y.data(), c->ds_y.p, n * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        double acc = 0;
+        for (uint64_t k = 0; k < n; ++k) acc += ((double)pr[k] - y[k]) * ((double)pr[k] - y[k]);
+        *mse = acc / (double)n;
+    }
+    return BH_OK;
+}
+
+bh_status bh_mlp_weights(bh_ctx *c, float *get, const float *set) {
+    if (!c) return BH_EINVAL;
+    HIPCHK(c, grow(c->mlp_w, BH_MLP_NPARAM * 4));
+    HIPCHK(c, hipDeviceSynchronize());
+    if (get) HIPCHK(c, hipMemcpy(get, c->mlp_w.p, BH_MLP_NPARAM * 4, hipMemcpyDeviceToHost));
+    if (set) {
+        HIPCHK(c, hipMemcpy(c->mlp_w.p, set, BH_MLP_NPARAM * 4, hipMemcpyHostToDevice));
+        c->mlp_ready = true;
+        c->lists_valid = false;
+    }
+    return BH_OK;
+}
+
+bh_status bh_mlp_dataset(bh_ctx *c, int64_t *n, uint32_t *pairs, float *x, float *y) {
+    if (!c) return BH_EINVAL;
+    if (n) *n = (int64_t)c->ds_n;
+    if (c->ds_n == 0) return BH_OK;
+    HIPCHK(c, hipDeviceSynchronize());
+    if (pairs) HIPCHK(c, hipMemcpy(pairs, c->ds_pairs.p, c->ds_n * sizeof(uint2), hipMemcpyDeviceToHost));
+    if (x) HIPCHK(c, hipMemcpy(x, c->ds_x.p, c->ds_n * sizeof(float4), hipMemcpyDeviceToHost));
+    if (y) HIPCHK(c, hipMemcpy(y, c->ds_y.p, c->ds_n * 4, hipMemcpyDeviceToHost));
+    return BH_OK;
+}
+
+bh_status bh_mlp_clear(bh_ctx *c) {
+    if (!c) return BH_EINVAL;
+    c->ds_n = 0;
+    return BH_OK;
+}
+
+bh_status bh_mlp_predict(bh_ctx *c, const float *x, int64_t n, float *out, void *stream) {
+    if (!c || (n > 0 && (!x || !out)) || n < 0) return BH_EINVAL;
+    bhk::mlp_eval(P<float>(c->mlp_w), reinterpret_cast<const float4 *>(x), (uint64_t)n, out, (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return BH_OK;
+}
+
+bh_status bh_mlp_gradient(bh_ctx *c, const float *x, const float *y, int32_t B, float *grad, float *loss,
+                          void *stream) {
+    if (!c || !x || !y || !grad || B < 1 || B > 65536) return BH_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    STCHK(ensure_mlp_train_buffers(c, (uint32_t)B, (uint64_t)B));
+    bhk::perm_keys(P<uint64_t>(c->pk_a), P<uint32_t>(c->pv_a), (uint64_t)B, 0, s);   // identity order
+    bhk::mlp_batch_grad(P<float>(c->mlp_w), reinterpret_cast<const float4 *>(x), y, P<uint32_t>(c->pv_a),
+                        (uint32_t)B, P<float>(c->act), grad, loss, s);
+    HIPCHK(c, hipGetLastError());
+    return BH_OK;
+}
+
 bh_status bh_query(const bh_ctx *c, bh_sizes *o) {
     if (!c || !o) return BH_EINVAL;
     o->n_particles = c->n;
@@ -885,6 +1179,30 @@ bh_status bh_export(bh_ctx *c, int32_t what, void *dst, void *stream) {
         return BH_OK;
     case BH_EXPORT_SORTED_POS:
         HIPCHK(c, hipMemcpy(dst, c->pos.p, n * sizeof(double4), hipMemcpyDeviceToHost));
+        return BH_OK;
+    case BH_EXPORT_QUAD:
+        if (!c->tree_valid || c->P.criterion != BH_OPEN_LEARNED) return fail(c, BH_ESTATE, "no second moments");
+        HIPCHK(c, hipMemcpy(dst, c->nd_quad.p, nn * 6 * sizeof(double), hipMemcpyDeviceToHost));
+        return BH_OK;
+    case BH_EXPORT_NODE_QN:
+        if (!c->tree_valid || c->P.criterion != BH_OPEN_LEARNED) return fail(c, BH_ESTATE, "no node features");
+        HIPCHK(c, hipMemcpy(dst, c->nd_qn.p, nn * 4, hipMemcpyDeviceToHost));
+        return BH_OK;
+    case BH_EXPORT_GROUP_EXTRA: {
+        if (!c->tree_valid || c->P.criterion != BH_OPEN_LEARNED) return fail(c, BH_ESTATE, "no group extras");
+        std::vector<double> r(ng), a(ng);
+        HIPCHK(c, hipMemcpy(r.data(), c->g_rad.p, ng * 8, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(a.data(), c->g_amin.p, ng * 8, hipMemcpyDeviceToHost));
+        double *o = (double *)dst;
+        for (size_t k = 0; k < ng; ++k) {
+            o[2 * k] = r[k];
+            o[2 * k + 1] = a[k];
+        }
+        return BH_OK;
+    }
+    case BH_EXPORT_ROOT_BOX:
+        if (!c->tree_valid) return fail(c, BH_ESTATE, "no tree");
+        HIPCHK(c, hipMemcpy(dst, c->box_b.p, (size_t)c->n_sys * sizeof(double4), hipMemcpyDeviceToHost));
         return BH_OK;
     default:
         return fail(c, BH_EINVAL, "unknown export item");

@@ -193,6 +193,7 @@ __global__ void __launch_bounds__(FT) k_force(DevState d, uint32_t ng) {
                     sp += red[3][ww][lane];
                 }
                 double gx = d.G * (double)sx, gy = d.G * (double)sy, gz = d.G * (double)sz;
+                if (d.amag) d.amag[i] = sqrt(gx * gx + gy * gy + gz * gz);
                 if (d.central_mass != 0.0) {
                     const double4 p = d.pos[i];
                     const double r2 = p.x * p.x + p.y * p.y + p.z * p.z;

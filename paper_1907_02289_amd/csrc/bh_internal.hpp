@@ -32,6 +32,9 @@ struct DevCounters {
     uint32_t work_counter;              // persistent-kernel work queue head
     uint32_t work_counter2;
     uint32_t pad[4];
+    unsigned long long cand_used;       // learned rule: candidate pairs recorded (may exceed capacity)
+    uint32_t work_counter3;
+    uint32_t pad2;
 };
 
 // ---------------------------------------------------------------- wave helpers
@@ -162,11 +165,25 @@ struct DevState {
     uint32_t *walk_scratch;        // per walking wave: 2 frontiers + 2 lists
     uint32_t walk_front_cap, walk_list_cap, walk_waves;
     DevCounters *cnt;
+    // learned opening rule
+    int walk_mode;                 // WALK_GEOMETRIC, WALK_LEARNED, WALK_ENUMERATE
+    double th2_min, th2_max, tau;  // band of the learned rule and its error budget
+    const float *mlp;              // MLP_NPARAM weights
+    float *nd_qn;                  // [node_cap] second-moment feature
+    double *amag, *amag_in;        // [n] |self-gravity acceleration| of the last evaluation (sorted / staging)
+    double *g_amin;                // [groups] mean amag of the group (error budget scale)
+    double *g_rad;                 // [groups] half-diagonal of the group's FP64 bounding box
+    uint2 *cand;                   // (group, node) candidate pairs recorded by the enumerating walk
+    unsigned long long cand_cap;
+    uint32_t group_stride;         // enumerating walk: record pairs of every group_stride-th group
+    uint32_t count_cap;            // nodes with more particles use the geometric rule
     // parameters
     int n_leaf, n_grp;
     double th2;                    // theta * theta
     double eps2, G, central_mass;
 };
+
+enum { WALK_GEOMETRIC = 0, WALK_LEARNED = 1, WALK_ENUMERATE = 2 };
 
 constexpr int BOX_BLOCKS = 64;
 
@@ -199,6 +216,18 @@ void kick_drift(const DevState &d, double h, double dt, hipStream_t s);
 void kick(const DevState &d, double h, hipStream_t s);
 void scatter_state(const DevState &d, hipStream_t s);
 void scatter_acc(const DevState &d, const AccPtr *tab, hipStream_t s);
+
+// learned opening rule (bh_learned.hip)
+void node_qn(const DevState &d, hipStream_t s);
+void group_amin(const DevState &d, hipStream_t s);
+void cand_features_labels(const DevState &d, uint64_t n_cand, float4 *X, float *Y, hipStream_t s);
+void mlp_stats(const float4 *X, const float *Y, uint64_t n, float *w, hipStream_t s);
+void mlp_batch_grad(const float *w, const float4 *X, const float *Y, const uint32_t *idx, uint32_t B,
+                    float *act, float *grad, float *loss, hipStream_t s);
+void mlp_adam(float *w, const float *grad, float *m, float *v, float lr, float b1, float b2, float eps,
+              int step, hipStream_t s);
+void mlp_eval(const float *w, const float4 *X, uint64_t n, float *out, hipStream_t s);
+void perm_keys(uint64_t *key, uint32_t *val, uint64_t n, uint64_t seed, hipStream_t s);
 
 // FP64 direct summation for sampled targets (bh_direct.hip)
 size_t direct_scratch_bytes(int64_t n_targets);

@@ -44,6 +44,7 @@ __global__ void k_load(DevState d) {
         d.pos_in[i] = make_double4(p.x[j], p.y[j], p.z[j], p.m[j]);
         d.vel_in[i] = p.vx ? make_double4(p.vx[j], p.vy[j], p.vz[j], 0.0) : make_double4(0.0, 0.0, 0.0, 0.0);
         d.idx_in[i] = i;
+        if (d.amag_in) d.amag_in[i] = INFINITY;      // unknown until a force evaluation
     }
 }
 
@@ -143,6 +144,7 @@ __global__ void k_permute(DevState d) {
         d.pos[j] = d.pos_in[src];
         d.vel[j] = d.vel_in[src];
         d.idx[j] = d.idx_in[src];
+        if (d.amag && d.amag_in) d.amag[j] = d.amag_in[src];
     }
 }
 
@@ -397,6 +399,16 @@ __global__ void __launch_bounds__(TPB) k_group_box(DevState d) {
             d.g_lo[g] = make_int4((int)qlo[0], (int)qlo[1], (int)qlo[2], 0);
             d.g_hi[g] = make_int4((int)qhi[0] + 1, (int)qhi[1] + 1, (int)qhi[2] + 1, 0);
             d.g_cen[g] = make_double4(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2]), 0.0);
+            if (d.g_rad) {
+                const double ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+                d.g_rad[g] = 0.5 * sqrt(ex * ex + ey * ey + ez * ez);
+            }
+        }
+        if (d.g_amin) {
+            double a = 0.0;
+            for (uint32_t i = gi.begin + __lane_id(); i < gi.begin + gi.count; i += 64) a += d.amag[i];
+            a = wave_sum(a) / (double)gi.count;
+            if (__lane_id() == 0) d.g_amin[g] = a;
         }
     }
 }

@@ -15,7 +15,7 @@
 // lies outside the group's grid box and side < theta * distance from the
 // node's centre to the box, evaluated in doubled integer grid units with a
 // single FP64 multiply, so every device decides exactly alike.
-#include "bh_internal.hpp"
+#include "bh_learned.hpp"
 
 namespace {
 
@@ -40,6 +40,38 @@ __device__ __forceinline__ bool accept_cell(int4 glo, int4 ghi, int Lx, int Ly, 
     return disjoint && ((double)s2 < th2 * (double)d2);
 }
 
+// Per-group constants of the learned rule.
+struct GroupCtx {
+    int4 glo, ghi;
+    double4 cen;
+    double rad, amin, Msys, S;
+};
+
+// Acceptance of node v for a group.  GEOMETRIC: the theta test.  LEARNED:
+// below theta_min accept, at or above theta_max open, in between the network
+// (single-particle nodes accepted, nodes above the count cap: the theta test).
+// ENUMERATE: the theta_min test; *cand reports whether (group, v) lies in the
+// band and is a training candidate.
+__device__ __forceinline__ bool decide(const DevState &d, const GroupCtx &gc, uint32_t v, int4 wr, bool *cand) {
+    const int level = (int)((uint32_t)wr.x >> 24);
+    const int Lx = wr.x & 0xffffff, Ly = wr.y & 0xffffff, Lz = wr.z;
+    *cand = false;
+    if (d.walk_mode == WALK_GEOMETRIC) return accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2);
+    if (accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2_min)) return true;
+    if (!accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2_max)) return false;
+    const uint32_t cnt = d.nd_count[v];
+    if (d.walk_mode == WALK_ENUMERATE) {
+        *cand = cnt >= 2 && cnt <= d.count_cap;
+        return false;
+    }
+    if (cnt == 1) return true;
+    if (cnt > d.count_cap) return accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2);
+    const double4 mom = d.nd_mom[v];
+    const PairGeom pg =
+        pair_features(mom, box_ratio2(gc.glo, gc.ghi, Lx, Ly, Lz, level), d.nd_qn[v], gc.cen, gc.rad, gc.Msys);
+    return learned_accept(d.mlp, pg, mom.w, gc.amin, d.tau, d.G);
+}
+
 __global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
     const uint32_t wave = (blockIdx.x * WALK_TPB + threadIdx.x) >> 6;
     if (wave >= d.walk_waves) return;
@@ -51,7 +83,6 @@ __global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
     uint32_t *pcb = fb + F;
     uint32_t *ppb = pcb + P;
     const uint32_t ng = d.cnt->n_groups;
-    const double th2 = d.th2;
 
     for (;;) {
         uint32_t g = 0;
@@ -59,7 +90,27 @@ __global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
         g = __shfl(g, 0, 64);
         if (g >= ng) break;
         const GroupInfo gi = d.grp[g];
-        const int4 glo = d.g_lo[g], ghi = d.g_hi[g];
+        GroupCtx gc;
+        gc.glo = d.g_lo[g];
+        gc.ghi = d.g_hi[g];
+        if (d.walk_mode != WALK_GEOMETRIC) {
+            gc.cen = d.g_cen[g];
+            gc.rad = d.g_rad[g];
+            gc.amin = d.walk_mode == WALK_LEARNED ? d.g_amin[g] : 0.0;
+            gc.Msys = d.nd_mom[gi.sys].w;
+            gc.S = (double)(1u << BH_MAXLEVEL) / d.box[gi.sys].w;
+        }
+        // the enumerating walk visits only the sampled groups and stores no lists
+        const bool enumerate = d.walk_mode == WALK_ENUMERATE;
+        const bool record = enumerate && (g % d.group_stride) == 0;
+        if (enumerate && !record) {
+            if (lane == 0) {
+                d.g_pc_len[g] = 0;
+                d.g_pp_len[g] = 0;
+                d.g_cost[g] = 0;
+            }
+            continue;
+        }
         uint32_t *cur = fa, *nxt = fb;
         if (lane == 0) cur[0] = gi.sys;          // root of the group's system
         __threadfence_block();
@@ -73,9 +124,17 @@ __global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
                 const bool valid = k < ncur;
                 const uint32_t v = valid ? cur[k] : 0u;
                 int4 wr = valid ? d.nd_walk[v] : make_int4(0, 0, 0, 0);
-                const int level = (int)((uint32_t)wr.x >> 24);
                 const int nch = (int)((uint32_t)wr.y >> 24);
-                const bool acc = valid && accept_cell(glo, ghi, wr.x & 0xffffff, wr.y & 0xffffff, wr.z, level, th2);
+                bool is_cand = false;
+                const bool acc = valid && decide(d, gc, v, wr, &is_cand);
+                is_cand = is_cand && valid && record;
+                const uint64_t mc = __ballot(is_cand);
+                if (mc) {
+                    unsigned long long at = 0;
+                    if (lane == 0) at = atomicAdd(&d.cnt->cand_used, (unsigned long long)__popcll(mc));
+                    at = __shfl(at, 0, 64) + (unsigned long long)__popcll(mc & lt);
+                    if (is_cand && at < d.cand_cap) d.cand[at] = make_uint2(g, v);
+                }
                 const bool is_pp = valid && !acc && nch == 0;
                 const uint32_t nopen = (valid && !acc && nch > 0) ? (uint32_t)nch : 0u;
 
@@ -83,8 +142,8 @@ __global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
                 const uint64_t mpp = __ballot(is_pp);
                 const uint32_t opc = npc + (uint32_t)__popcll(mpc & lt);
                 const uint32_t opp = npp + (uint32_t)__popcll(mpp & lt);
-                if (acc && opc < P) pcb[opc] = v;
-                if (is_pp && opp < P) ppb[opp] = v;
+                if (acc && opc < P && !enumerate) pcb[opc] = v;
+                if (is_pp && opp < P && !enumerate) ppb[opp] = v;
                 unsigned long long cnt_pp = is_pp ? (unsigned long long)d.nd_count[v] : 0ull;
                 pp_particles += wave_sum(cnt_pp);
                 npc += (uint32_t)__popcll(mpc);
@@ -97,7 +156,7 @@ __global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
                     if (o + c < F) nxt[o + c] = (uint32_t)wr.w + c;
                 nnext += tot;
             }
-            if (nnext > F || npc > P || npp > P) ovf = true;
+            if (nnext > F || (!enumerate && (npc > P || npp > P))) ovf = true;
             __threadfence_block();
             uint32_t *t = cur; cur = nxt; nxt = t;
             ncur = nnext;
@@ -106,11 +165,19 @@ __global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
             if (lane == 0) {
                 atomicOr(&d.cnt->flags[FLAG_WALK_OVF], 1u);
                 atomicMax(&d.cnt->walk_need_front, ncur);
-                atomicMax(&d.cnt->walk_need_list, max(npc, npp));
+                if (!enumerate) atomicMax(&d.cnt->walk_need_list, max(npc, npp));
             }
             d.g_pc_len[g] = 0;
             d.g_pp_len[g] = 0;
             d.g_cost[g] = 0;
+            continue;
+        }
+        if (enumerate) {
+            if (lane == 0) {
+                d.g_pc_len[g] = 0;
+                d.g_pp_len[g] = 0;
+                d.g_cost[g] = 0;
+            }
             continue;
         }
         unsigned long long at_pc = 0, at_pp = 0;
@@ -150,6 +217,7 @@ __global__ void k_walk_reset(DevState d) {
         d.cnt->walk_need_list = 0;
         d.cnt->flags[FLAG_WALK_OVF] = 0;
         d.cnt->flags[FLAG_POOL_OVF] = 0;
+        d.cnt->cand_used = 0;
     }
 }
 

@@ -1,0 +1,172 @@
+"""Pins for the oracle of the learned opening rule (an addition to the paper's
+walk): the lg2p scale, the features, the exact labels (closed form for a
+two-particle node), the FP32 network against an FP64 evaluation, the
+training gradient against finite differences, and the learned walk in its
+two limits (accept the whole band / open the whole band), which reduce to
+geometric walks with known definitions."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_1907_02289_amd import inputs
+
+
+def test_lg2p_scale():
+    for e in range(-60, 60, 7):
+        assert oracle.lg2p(2.0 ** e) == e
+    xs = np.sort(np.random.default_rng(0).uniform(1e-6, 1e6, 2000))
+    v = [oracle.lg2p(x) for x in xs]
+    assert all(b >= a for a, b in zip(v, v[1:]))
+    for x in xs[::50]:
+        # max of log2(x) - (x - 1) on [1, 2) at x = 1/ln 2
+        assert 0.0 <= math.log2(x) - oracle.lg2p(x) <= 1 / math.log(2) - 1 - math.log2(math.log(2)) + 1e-12
+    assert oracle.lg2p(0.0) == -1100.0 and oracle.lg2p(math.inf) == 1100.0
+
+
+def test_features_closed_form():
+    Q = np.array([1.0, 0.0, 0.0, 1.0, 0.0, 1.0])            # xx, xy, xz, yy, yz, zz
+    M, side = 0.5, 0.25
+    qn = oracle.node_qn(Q, M, side)
+    assert qn == np.float32(math.sqrt(3.0) / (M * side * side))
+    f, d2 = oracle.features([3.0, 4.0, 0.0], M, 0.04, qn, [0.0, 0.0, 0.0], 2.5, 2.0)
+    assert d2 == 25.0
+    lg = oracle.lg2p
+    assert list(f) == [np.float32(lg(0.04)), np.float32(lg(0.5)), np.float32(-2.0), np.float32(lg(float(qn)))]
+    assert f[1] == -1.0 and f[2] == -2.0
+    # box ratio: a level-3 node (side 2^18) whose centre lies 3 sides from a unit group box along x
+    s = 1 << 18
+    gb = np.array([0, 0, 0, 1, s, s], np.int32)              # [0,1) x [0,s) x [0,s)
+    pfx = 0b100                                                # octant x=1 at the finest of 3 levels
+    # node 3 at level 3 along x: corner x = 1 * 2^18 ... choose the node at corner x = 4s
+    pfx = (0b100 << 6)                                         # x bit set at level 1 -> corner x = 2^20 = 4s
+    c2 = 2 * (4 * s) + s                                       # doubled centre
+    d2 = (c2 - 2 * 1) ** 2 + 0 + 0                            # doubled distance to the face x = 1 (y, z inside)
+    assert oracle.box_ratio2(gb, 3, pfx) == (2 * s) ** 2 / d2
+
+
+def test_label_two_particle_node_closed_form():
+    # node: masses m at (-a, 0, 0) and (a, 0, 0); group: one particle at (D, 0, 0)
+    a, D, m, G = 0.1, 1.3, 0.25, 1.0
+    x = np.array([-a, a, D])
+    y = np.zeros(3)
+    z = np.zeros(3)
+    ms = np.array([m, m, 1.0])
+    com4 = np.array([0.0, 0.0, 0.0, 2 * m])
+    got = oracle.label_ratio(2, 1, 0, 2, x, y, z, ms, com4, [D, 0.0, 0.0], 0.0, G)
+    want = 0.5 * (D * D / (D - a) ** 2 + D * D / (D + a) ** 2) - 1.0
+    assert abs(got - want) <= 1e-13 * want
+    # a single-particle node is its own monopole: zero error
+    assert oracle.label_ratio(2, 1, 1, 1, x, y, z, ms, np.array([a, 0.0, 0.0, m]), [D, 0, 0], 0.0, G) == 0.0
+
+
+def _random_weights(rng):
+    w = np.zeros(1259, np.float32)
+    w[:1249] = rng.normal(0, 0.4, 1249)
+    w[1249:1253] = rng.normal(0, 0.2, 4)
+    w[1253:1257] = rng.uniform(0.5, 2.0, 4)
+    w[1257], w[1258] = -3.0, 2.0
+    return w
+
+
+def test_network_fp32_against_fp64():
+    rng = np.random.default_rng(1)
+    w = _random_weights(rng)
+    X = rng.normal(0, 1, (500, 4)).astype(np.float32)
+    f32 = oracle.mlp_forward(w, X)
+    f64 = mlp.forward(w, X)
+    scale = np.abs(f64) + 2.0 * np.abs(w[1258]) * 1.0
+    assert np.max(np.abs(f32 - f64) / scale) < 2e-5
+
+
+def test_network_hand_set_closed_form():
+    w = np.zeros(1259, np.float32)
+    w[1253:1257] = 1.0
+    w[mlp.W1 + 0] = 1.0                 # h1_0 = relu(x0)
+    w[mlp.W2 + 0] = 2.0                 # h2_0 = relu(2 h1_0)
+    w[mlp.W3 + 0] = 3.0                 # out = 3 h2_0 + b3
+    w[mlp.B3] = -1.0
+    w[1257], w[1258] = 0.5, 4.0         # y = out * 4 + 0.5
+    X = np.array([[1.5, 9, 9, 9], [-2.0, 9, 9, 9]], np.float32)
+    assert list(oracle.mlp_forward(w, X)) == [np.float32((3 * 2 * 1.5 - 1) * 4 + 0.5), np.float32(-1 * 4 + 0.5)]
+
+
+def test_training_gradient_finite_differences():
+    rng = np.random.default_rng(2)
+    w = _random_weights(rng).astype(np.float64)
+    X = rng.normal(0, 1, (64, 4))
+    Y = rng.normal(-3, 2, 64)
+    loss, g = mlp.loss_and_grad(w, X, Y)
+    h = 1e-6
+    for p in list(range(0, 1249, 37)) + [1248]:
+        wp, wm = w.copy(), w.copy()
+        wp[p] += h
+        wm[p] -= h
+        fd = (mlp.loss_and_grad(wp, X, Y)[0] - mlp.loss_and_grad(wm, X, Y)[0]) / (2 * h)
+        assert abs(fd - g[p]) <= 1e-6 * (1 + abs(g[p])), p
+
+
+def _accept_exact(gb, lvl, pfx, theta):
+    """Geometric opening test in exact rationals: outside the group box and
+    side < theta * distance(node centre, box)."""
+    from fractions import Fraction
+    side = 1 << (21 - lvl)
+    corner = [0, 0, 0]
+    for k in range(lvl):
+        for a in range(3):
+            corner[a] |= ((pfx >> (3 * k + 2 - a)) & 1) << k
+    corner = [c << (21 - lvl) for c in corner]
+    outside = any(corner[a] + side <= gb[a] or corner[a] >= gb[3 + a] for a in range(3))
+    d2 = Fraction(0)
+    for a in range(3):
+        c = Fraction(corner[a]) + Fraction(side, 2)
+        near = min(max(c, Fraction(int(gb[a]))), Fraction(int(gb[3 + a])))
+        d2 += (c - near) ** 2
+    return outside and Fraction(side) ** 2 < Fraction(theta) ** 2 * d2
+
+
+def _setup(n=1500, seed=3, n_grp=32):
+    s = inputs.ring(n, seed)
+    st = oracle.BHState(s.x, s.y, s.z, s.m, 0.5, 8, n_grp, with_q=True)
+    t = st.tree
+    xs, ys, zs = (a[st.perm] for a in (s.x, s.y, s.z))
+    com4 = np.stack([st.mom["cx"], st.mom["cy"], st.mom["cz"], st.mom["M"]], 1)
+    qn = np.array([oracle.node_qn(st.mom["Q"][v], st.mom["M"][v], st.S * 2.0 ** -int(t["level"][v]))
+                   for v in range(t["begin"].size)], np.float32)
+    grad = np.array([0.5 * math.sqrt(sum((a[b:b + c].max() - a[b:b + c].min()) ** 2 for a in (xs, ys, zs)))
+                     for b, c in zip(t["begin"][st.gnode], t["count"][st.gnode])])
+    gamin = np.full(st.gnode.size, 0.3)
+    return st, t, com4, qn, grad, gamin
+
+
+@pytest.mark.parametrize("bias,theta_ref", [(-1000.0, 0.8), (1000.0, 0.3)])
+def test_learned_walk_limits(bias, theta_ref):
+    """Output -1000 accepts the whole band: the geometric walk at theta_max.
+    Output +1000 opens it: the geometric walk at theta_min, except that a
+    single-particle node in the band is accepted (its monopole is exact)."""
+    st, t, com4, qn, grad, gamin = _setup()
+    w = np.zeros(1259, np.float32)
+    w[1253:1257] = 1.0
+    w[1258] = 1.0
+    w[mlp.B3] = bias
+    th_min, th_max = 0.3, 0.8
+    got = oracle.lists_learned(st.gbox, st.gcen, grad, gamin, t, com4, qn, w, st.S, theta=th_max,
+                               theta_min=th_min, theta_max=th_max, tau=1e-3)
+    ref = oracle.lists(st.gbox, t, theta_ref)
+    if bias < 0:
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(a, b)
+        return
+    # +1000: a single-particle leaf of the theta_min particle list that passes
+    # the theta_max test lies in the band and moves to the node list
+    for g in range(st.gnode.size):
+        pc_ref = set(ref[1][ref[0][g]:ref[0][g + 1]].tolist())
+        pp_ref = set(ref[3][ref[2][g]:ref[2][g + 1]].tolist())
+        moved = {v for v in pp_ref if t["count"][v] == 1 and
+                 _accept_exact(st.gbox[g], int(t["level"][v]), int(t["prefix"][v]), th_max)}
+        pc_got = got[1][got[0][g]:got[0][g + 1]].tolist()
+        pp_got = got[3][got[2][g]:got[2][g + 1]].tolist()
+        assert pc_got == sorted(pc_ref | moved)
+        assert pp_got == sorted(pp_ref - moved)
