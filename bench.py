@@ -205,7 +205,8 @@ def main():
     ap.add_argument("--theta-tuned", type=float, default=None, help="skip tuning, use this theta (tuned path)")
     ap.add_argument("--theta-plain", type=float, default=None, help="skip tuning, use this theta (plain path)")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-criterion form")
+    ap.add_argument("--learned", action="store_true",
+                    help="also train, tune and time the learned-criterion form (off by default: see the design notes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: sharding the groups "
@@ -302,7 +303,7 @@ def main():
     tu = timed(paths["tuned"], args.steps, args.warmup, R)
     log(f"[bench] tuned: {tu}")
     lr = None
-    if not args.no_learned:
+    if args.learned:
         lp = learned_path(bh, inputs, w, dev0, sample, ref, n, paths["tuned"], args)
         lr = timed(lp, max(1, args.steps // 2), 1, R)
         log(f"[bench] learned: {lr}")

@@ -506,7 +506,9 @@ bh_status make_lists(bh_ctx *c, hipStream_t s) {
     return order_lists(c, s);
 }
 
-int force_blocks(const bh_ctx *c) { return c->n_cu * 8; }
+// Persistent workgroups of the force kernel: as many as stay resident (FP32:
+// 6 per CU by its register cap; FP64: 4 at its register use).
+int force_blocks(const bh_ctx *c) { return c->n_cu * (c->P.precision == BH_FP32_REL ? 6 : 4); }
 
 bh_status run_forces(bh_ctx *c, hipStream_t s, bool pot) {
     if (c->force_ev_used == c->force_ev.size()) {

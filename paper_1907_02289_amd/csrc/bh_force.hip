@@ -15,10 +15,13 @@
 // queue in order of decreasing interaction count, so the longest lists start
 // first and the tail is made of short ones.  All four waves of a workgroup
 // share one LDS tile of sources (the paper's cores sharing a cache on one
-// list): a group of up to 64 particles has its source range split four ways
-// over the waves, up to 128 two ways, larger groups one i-chunk per wave;
-// the per-wave partial sums are added in a fixed order, so results do not
-// depend on timing.
+// list).  A group of more than 64 particles gives each wave a 64-particle
+// chunk, the waves left over splitting the source range; a group of at most
+// 64 (32, 16) particles splits the source range over the four waves (and
+// over 2 or 4 sub-slices of 32 or 16 lanes inside each wave, the tile padded
+// with massless sources), so small groups do not leave most lanes idle.
+// Partial sums are added in a fixed order, so results do not depend on
+// timing.
 #include "bh_internal.hpp"
 
 namespace {
@@ -53,11 +56,16 @@ __device__ __forceinline__ float fma_r<float>(float a, float b, float c) { retur
 template <>
 __device__ __forceinline__ double fma_r<double>(double a, double b, double c) { return fma(a, b, c); }
 
-// One pass of a wave over sources [j0, j1) of the LDS tile.
+// One pass of a wave over sources [j0, j1) of the LDS tile.  The bounds are
+// the same for every lane of the wave; taking them through readfirstlane
+// keeps the loop control on the scalar unit, so the vector unit issues only
+// the pair arithmetic (every lane reads the same LDS entry: a broadcast).
 template <typename R, bool POT, bool ZERO_EPS>
 __device__ __forceinline__ void interact(const typename V4<R>::T *tile, int j0, int j1, R xi, R yi, R zi, R eps2,
                                          R &ax, R &ay, R &az, R &pot) {
-#pragma unroll 4
+    j0 = __builtin_amdgcn_readfirstlane(j0);
+    j1 = __builtin_amdgcn_readfirstlane(j1);
+#pragma unroll 8
     for (int j = j0; j < j1; ++j) {
         const typename V4<R>::T s = tile[j];
         const R dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
@@ -73,10 +81,41 @@ __device__ __forceinline__ void interact(const typename V4<R>::T *tile, int j0, 
     }
 }
 
+// The same pass when the lanes of a wave work on different source ranges
+// (sub-slices of a small group): lane base jb, common length L.
 template <typename R, bool POT, bool ZERO_EPS>
-__global__ void __launch_bounds__(FT) k_force(DevState d, uint32_t ng) {
+__device__ __forceinline__ void interact_lanes(const typename V4<R>::T *tile, int jb, int L, R xi, R yi, R zi,
+                                               R eps2, R &ax, R &ay, R &az, R &pot) {
+    L = __builtin_amdgcn_readfirstlane(L);
+    const typename V4<R>::T *t = tile + jb;
+#pragma unroll 8
+    for (int k = 0; k < L; ++k) {
+        const typename V4<R>::T s = t[k];
+        const R dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+        const R r2 = fma_r<R>(dx, dx, fma_r<R>(dy, dy, fma_r<R>(dz, dz, eps2)));
+        R ri = rsqrt_r<R>(r2);
+        if (ZERO_EPS) ri = (r2 > (R)0) ? ri : (R)0;
+        const R mri = s.w * ri;
+        const R f = mri * (ri * ri);
+        ax = fma_r<R>(f, dx, ax);
+        ay = fma_r<R>(f, dy, ay);
+        az = fma_r<R>(f, dz, az);
+        if (POT) pot -= mri;
+    }
+}
+
+// FP32: registers capped so that 6 workgroups (24 waves) fit a CU; the
+// pair loop needs the occupancy to hide LDS and rsqrt latency (measured:
+// 100 VGPRs / 4 waves per SIMD ran 18% slower).  FP64 keeps the default.
+template <typename R>
+struct ForceOcc {
+    static constexpr int blocks = sizeof(R) == 4 ? 6 : 1;
+};
+
+template <typename R, bool POT, bool ZERO_EPS>
+__global__ void __launch_bounds__(FT, ForceOcc<R>::blocks) k_force(DevState d, uint32_t ng) {
     using T4 = typename V4<R>::T;
-    __shared__ T4 tile[TJ];
+    __shared__ T4 tile[TJ + 16];
     __shared__ uint32_t lbeg[TJ];
     __shared__ uint32_t lscan[TJ + 1];
     __shared__ R red[4][4][64];
@@ -91,10 +130,12 @@ __global__ void __launch_bounds__(FT) k_force(DevState d, uint32_t ng) {
     for (;;) {
         if (tid == 0) s_item = atomicAdd(&d.cnt->work_counter2, 1u);
         __syncthreads();
-        const uint32_t item = s_item;
+        // the work item is the same for the whole workgroup: keep it (and all
+        // per-group values derived from it) in scalar registers
+        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (item >= ng) break;
-        const uint32_t g = d.order[item];
+        const uint32_t g = __builtin_amdgcn_readfirstlane(d.order[item]);
         const GroupInfo gi = d.grp[g];
         const double4 cen = d.g_cen[g];
         const unsigned long long pc0 = d.g_pc_off[g], pp0 = d.g_pp_off[g];
@@ -102,12 +143,18 @@ __global__ void __launch_bounds__(FT) k_force(DevState d, uint32_t ng) {
 
         for (uint32_t ib = 0; ib < gi.count; ib += FT) {
             const uint32_t nb = min((uint32_t)FT, gi.count - ib);
-            const int n_ic = (int)((nb + 63) >> 6);
+            // lanes per particle chunk: a group of <= 16 (<= 32) particles splits
+            // each wave into 4 (2) sub-slices of the source range
+            const int cw = nb <= 16 ? 16 : (nb <= 32 ? 32 : 64);
+            const int sub = 64 / cw;
+            const int n_ic = cw < 64 ? 1 : (int)((nb + 63) >> 6);
             const int split = 4 / n_ic;
             const int ichunk = w % n_ic;
             const int jslice = w / n_ic;
             const bool wave_on = jslice < split;
-            const uint32_t il = ichunk * 64 + lane;
+            const int nslices = split * sub;
+            const int slice = jslice * sub + lane / cw;
+            const uint32_t il = cw < 64 ? (uint32_t)(lane % cw) : ichunk * 64 + lane;
             const bool ion = wave_on && il < nb;
             const uint32_t i = gi.begin + ib + il;
             R xi = 0, yi = 0, zi = 0;
@@ -119,6 +166,26 @@ __global__ void __launch_bounds__(FT) k_force(DevState d, uint32_t ng) {
             }
             R ax = 0, ay = 0, az = 0, pot = 0;
 
+            // The staged tile holds cntt sources: pad it with massless far
+            // sources to a whole number of sub-slices, then let every active
+            // wave (or sub-slice) run over its share.
+            auto compute_tile = [&](uint32_t cntt) {
+                const int L = ((int)cntt + nslices - 1) / nslices;
+                if (cw < 64)
+                    for (int t = (int)cntt + tid; t < L * nslices; t += FT)
+                        tile[t] = mk4<R>((R)1e18, (R)1e18, (R)1e18, (R)0);
+                __syncthreads();
+                if (wave_on) {
+                    if (cw == 64) {
+                        const int j0 = (int)(cntt * jslice / split), j1 = (int)(cntt * (jslice + 1) / split);
+                        interact<R, POT, ZERO_EPS>(tile, j0, j1, xi, yi, zi, eps2, ax, ay, az, pot);
+                    } else {
+                        interact_lanes<R, POT, ZERO_EPS>(tile, slice * L, L, xi, yi, zi, eps2, ax, ay, az, pot);
+                    }
+                }
+                __syncthreads();
+            };
+
             // ---- node list: centre of mass and mass of each accepted node
             for (uint32_t t0 = 0; t0 < npc; t0 += TJ) {
                 const uint32_t cntt = min((uint32_t)TJ, npc - t0);
@@ -126,12 +193,7 @@ __global__ void __launch_bounds__(FT) k_force(DevState d, uint32_t ng) {
                     const double4 m = d.nd_mom[d.pc_pool[pc0 + t0 + tid]];
                     tile[tid] = mk4<R>((R)(m.x - cen.x), (R)(m.y - cen.y), (R)(m.z - cen.z), (R)m.w);
                 }
-                __syncthreads();
-                if (wave_on) {
-                    const int j0 = (int)(cntt * jslice / split), j1 = (int)(cntt * (jslice + 1) / split);
-                    interact<R, POT, ZERO_EPS>(tile, j0, j1, xi, yi, zi, eps2, ax, ay, az, pot);
-                }
-                __syncthreads();
+                compute_tile(cntt);
             }
 
             // ---- particle list: the particles of each listed leaf
@@ -168,22 +230,27 @@ __global__ void __launch_bounds__(FT) k_force(DevState d, uint32_t ng) {
                         const double4 q = d.pos[lbeg[lo] + (f - lscan[lo])];
                         tile[tid] = mk4<R>((R)(q.x - cen.x), (R)(q.y - cen.y), (R)(q.z - cen.z), (R)q.w);
                     }
-                    __syncthreads();
-                    if (wave_on) {
-                        const int j0 = (int)(cntt * jslice / split), j1 = (int)(cntt * (jslice + 1) / split);
-                        interact<R, POT, ZERO_EPS>(tile, j0, j1, xi, yi, zi, eps2, ax, ay, az, pot);
-                    }
-                    __syncthreads();
+                    compute_tile(cntt);
                 }
             }
 
             // ---- add the j-slices in a fixed order and write FP64 results
+            if (cw < 64) {
+#pragma unroll
+                for (int off = 32; off >= 16; off >>= 1) {
+                    if (off < cw) break;
+                    ax += __shfl_xor(ax, off, 64);
+                    ay += __shfl_xor(ay, off, 64);
+                    az += __shfl_xor(az, off, 64);
+                    pot += __shfl_xor(pot, off, 64);
+                }
+            }
             red[0][w][lane] = ax;
             red[1][w][lane] = ay;
             red[2][w][lane] = az;
             red[3][w][lane] = pot;
             __syncthreads();
-            if (ion && jslice == 0) {
+            if (ion && jslice == 0 && lane < cw) {
                 R sx = 0, sy = 0, sz = 0, sp = 0;
                 for (int k = 0; k < split; ++k) {
                     const int ww = k * n_ic + ichunk;

@@ -242,8 +242,8 @@ void radix_sort(uint64_t *key_a, uint32_t *val_a, uint64_t *key_b, uint32_t *val
     if (sys_off && n_sys > 1)
         for (int sh = 0; (n_sys - 1) >> sh; sh += 8) pass(true, sh);
     if (passes & 1) {
-        hipMemcpyAsync(key_a, ki, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
-        hipMemcpyAsync(val_a, vi, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        (void)hipMemcpyAsync(key_a, ki, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+        (void)hipMemcpyAsync(val_a, vi, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
     }
 }
 

@@ -251,7 +251,7 @@ void order_groups(const DevState &d, uint32_t n_groups, uint64_t *key_a, uint32_
     if (blocks > 4096) blocks = 4096;
     k_order_keys<<<blocks, 256, 0, s>>>(d, key_a, val_a);
     radix_sort(key_a, val_a, key_b, val_b, n_groups, 0, 40, d.hist, d.scan_tmp, s, nullptr, 0);
-    hipMemcpyAsync(d.order, val_a, (size_t)n_groups * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(d.order, val_a, (size_t)n_groups * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
 }
 
 }  // namespace bhk
