@@ -46,9 +46,9 @@ def lib():
         L.orc_groups.restype = i64
         L.orc_group_boxes.argtypes = [i64, P, P, P, P, P, P, P, P, P]
         L.orc_lists.argtypes = [i64, P, P, P, P, P, dbl, P, P, P, P]
-        L.orc_forces.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P,
-                                 dbl, dbl, P, P, P, P, P]
-        L.orc_direct.argtypes = [i64, P, P, P, P, dbl, dbl, i64, P, P, P, P, P]
+        L.orc_forces.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, dbl, dbl, P, P, P, dbl, dbl, dbl,
+                                 P, P, P, P, P]
+        L.orc_direct.argtypes = [i64, P, P, P, P, dbl, dbl, i64, P, P, P, P, dbl, dbl, dbl, P, P, P, P]
         L.orc_central.argtypes = [i64, P, P, P, dbl, dbl, P, P, P]
         L.orc_threads.restype = C.c_int
         L.orc_lg2p.argtypes = [dbl]
@@ -162,27 +162,46 @@ def lists(gbox, t, theta):
     return pc_off, pc[: pc_off[-1]].copy(), pp_off, pp[: pp_off[-1]].copy()
 
 
-def forces(gnode, t, xs, ys, zs, ms, mom, pc_off, pc, pp_off, pp, eps, G=1.0):
+def _contact_args(contact, vel, n):
+    """(vx, vy, vz, rc, kappa, eta) for the C calls; contact = (rc, kappa, eta)
+    switches on the collision branch of Eq. (2) and then needs vel = (vx, vy, vz)."""
+    if contact is None or contact[0] <= 0.0:
+        return (None, None, None, 0.0, 0.0, 0.0), ()
+    if vel is None:
+        raise ValueError("the collision branch needs velocities")
+    v = tuple(_f64(a) for a in vel)
+    assert all(a.size == n for a in v)
+    rc, kappa, eta = (float(a) for a in contact)
+    return (_p(v[0]), _p(v[1]), _p(v[2]), rc, kappa, eta), v
+
+
+def forces(gnode, t, xs, ys, zs, ms, mom, pc_off, pc, pp_off, pp, eps, G=1.0, vel=None, contact=None):
+    """Barnes-Hut sums over the lists (arrays in sorted order).  contact =
+    (rc, kappa, eta) adds the collision branch of Eq. (2) for particle
+    sources, with vel = (vx, vy, vz) in sorted order."""
     n = xs.size
     ax, ay, az, pot, mag = (np.zeros(n) for _ in range(5))
     xs, ys, zs, ms = _f64(xs), _f64(ys), _f64(zs), _f64(ms)
+    cargs, _keep = _contact_args(contact, vel, n)
     pc = np.ascontiguousarray(pc, np.uint32) if pc.size else np.zeros(1, np.uint32)
     pp = np.ascontiguousarray(pp, np.uint32) if pp.size else np.zeros(1, np.uint32)
     lib().orc_forces(gnode.size, _p(gnode), _p(t["begin"]), _p(t["count"]),
                      _p(xs), _p(ys), _p(zs), _p(ms),
                      _p(mom["M"]), _p(mom["cx"]), _p(mom["cy"]), _p(mom["cz"]),
-                     _p(pc_off), _p(pc), _p(pp_off), _p(pp), float(eps), float(G),
+                     _p(pc_off), _p(pc), _p(pp_off), _p(pp), float(eps), float(G), *cargs,
                      _p(ax), _p(ay), _p(az), _p(pot), _p(mag))
     return ax, ay, az, pot, mag
 
 
-def direct(x, y, z, m, eps, G=1.0, targets=None):
-    """O(N * n_targets) direct sum; returns (ax, ay, az, pot) per target."""
+def direct(x, y, z, m, eps, G=1.0, targets=None, vel=None, contact=None):
+    """O(N * n_targets) direct sum; returns (ax, ay, az, pot) per target.
+    contact = (rc, kappa, eta) with vel = (vx, vy, vz): Eq. (2) with both branches."""
     x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
     tg = None if targets is None else np.ascontiguousarray(targets, np.int64)
     nt = x.size if tg is None else tg.size
+    cargs, _keep = _contact_args(contact, vel, x.size)
     ax, ay, az, pot = (np.zeros(nt) for _ in range(4))
-    lib().orc_direct(x.size, _p(x), _p(y), _p(z), _p(m), float(eps), float(G), nt, _p(tg),
+    lib().orc_direct(x.size, _p(x), _p(y), _p(z), _p(m), float(eps), float(G), nt, _p(tg), *cargs,
                      _p(ax), _p(ay), _p(az), _p(pot))
     return ax, ay, az, pot
 
@@ -212,10 +231,11 @@ class BHState:
         xs, ys, zs, ms = (np.asarray(a)[self.perm] for a in (x, y, z, m))
         self.mom = moments(self.tree, xs, ys, zs, ms, "Q" in self.mom)
 
-    def accel(self, x, y, z, m, eps, G=1.0):
+    def accel(self, x, y, z, m, eps, G=1.0, vel=None, contact=None):
         xs, ys, zs, ms = (np.asarray(a)[self.perm] for a in (x, y, z, m))
+        vs = None if vel is None else tuple(np.asarray(a)[self.perm] for a in vel)
         ax, ay, az, pot, mag = forces(self.gnode, self.tree, xs, ys, zs, ms, self.mom,
-                                      self.pc_off, self.pc, self.pp_off, self.pp, eps, G)
+                                      self.pc_off, self.pc, self.pp_off, self.pp, eps, G, vs, contact)
         out = [np.empty_like(ax) for _ in range(5)]
         for o, a in zip(out, (ax, ay, az, pot, mag)):
             o[self.perm] = a
@@ -231,24 +251,28 @@ class BHState:
         return int(np.sum(ng * (pp_len + pc_len)))
 
 
-def bh_accel(x, y, z, m, theta, eps, n_leaf=8, n_grp=64, G=1.0):
+def bh_accel(x, y, z, m, theta, eps, n_leaf=8, n_grp=64, G=1.0, vel=None, contact=None):
     """Full Barnes-Hut force in caller order: (ax, ay, az, pot, magsum, state)."""
     st = BHState(x, y, z, m, theta, n_leaf, n_grp)
-    return (*st.accel(x, y, z, m, eps, G), st)
+    return (*st.accel(x, y, z, m, eps, G, vel, contact), st)
 
 
-def direct_accel(x, y, z, m, eps, G=1.0):
-    ax, ay, az, pot = direct(x, y, z, m, eps, G)
+def direct_accel(x, y, z, m, eps, G=1.0, vel=None, contact=None):
+    ax, ay, az, pot = direct(x, y, z, m, eps, G, vel=vel, contact=contact)
     return ax, ay, az, pot
 
 
 def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
-        theta=None, n_leaf=8, n_grp=64, rebuild_every=1):
+        theta=None, n_leaf=8, n_grp=64, rebuild_every=1, contact=None, trace=None):
     """Kick-drift-kick leapfrog in FP64 (the integration step (4) of Sec. 4.2).
 
     theta=None uses the direct sum; otherwise Barnes-Hut with lists rebuilt
     every `rebuild_every` steps and moments refreshed on the other steps.
-    Returns new copies of (x, y, z, vx, vy, vz).
+    contact = (rc, kappa, eta) adds the collision branch of Eq. (2); its
+    dashpot sees the velocities held when the force is evaluated: the
+    initial ones for the first evaluation, the half-kicked ones after each
+    drift.  trace, if given, is called as trace(step, x, y, z, vx, vy, vz)
+    after every completed step.  Returns new copies of (x, y, z, vx, vy, vz).
     """
     x, y, z, vx, vy, vz = (np.array(a, dtype=np.float64, copy=True) for a in (x, y, z, vx, vy, vz))
     m = _f64(m)
@@ -256,14 +280,15 @@ def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
 
     def acc(step):
         nonlocal state
+        vel = (vx, vy, vz) if contact is not None else None
         if theta is None:
-            ax, ay, az, _ = direct(x, y, z, m, eps, G)
+            ax, ay, az, _ = direct(x, y, z, m, eps, G, vel=vel, contact=contact)
         else:
             if state is None or step % rebuild_every == 0:
                 state = BHState(x, y, z, m, theta, n_leaf, n_grp)
             else:
                 state.refresh(x, y, z, m)
-            ax, ay, az, _, _ = state.accel(x, y, z, m, eps, G)
+            ax, ay, az, _, _ = state.accel(x, y, z, m, eps, G, vel, contact)
         if central_mass:
             central(x, y, z, central_mass, G, ax, ay, az)
         return ax, ay, az
@@ -281,6 +306,8 @@ def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
         vx += h * ax
         vy += h * ay
         vz += h * az
+        if trace is not None:
+            trace(k, x, y, z, vx, vy, vz)
     return x, y, z, vx, vy, vz
 
 

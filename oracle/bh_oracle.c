@@ -386,15 +386,34 @@ void orc_lists(int64_t n_groups, const int32_t *gbox, const uint8_t *level, cons
 }
 
 /* ------------------------------------------------------------------ */
-/* Forces (Sec. 4.2 (3d) double loop; Sec. 5.1 Eq. (2), gravity branch  */
-/* with Plummer softening in place of the collision radius).  The       */
-/* acceleration of i from a source of mass mj at xj is                  */
-/*     G mj (xj - xi) / (|xj - xi|^2 + eps^2)^(3/2),                    */
-/* and its potential -G mj / sqrt(|xj - xi|^2 + eps^2).  Sources are    */
-/* the particles of the particle-list leaves and the centres of mass of */
-/* the node-list cells.  magsum[i] accumulates |term| (a scale for      */
-/* parity tolerances).  All arrays are in sorted (tree) order.          */
+/* Forces (Sec. 4.2 (3d) double loop; Sec. 5.1 Eq. (2)).  The          */
+/* acceleration of i from a source of mass mj at xj, r = |xj - xi|,     */
+/* rij = xj - xi, is the gravity branch with Plummer softening          */
+/*     G mj rij / (r^2 + eps^2)^(3/2),                                  */
+/* and its potential -G mj / sqrt(r^2 + eps^2).  Sources are the        */
+/* particles of the particle-list leaves and the centres of mass of the */
+/* node-list cells.                                                     */
+/*                                                                      */
+/* Collision branch (particle sources only, when rc > 0): for a pair    */
+/* with r <= rc (decided as dx*dx + dy*dy + dz*dz <= rc*rc, summed left */
+/* to right) Eq. (2) replaces the term by                               */
+/*     [ G mj / (rc^2 + eps^2)^(3/2)                                     */
+/*       + mj/(mi + mj) (kappa (r - rc)/r + eta (rij . vij)/r^2) ] rij, */
+/* vij = vj - vi: gravity frozen at its value on the contact sphere (at */
+/* eps = 0 exactly the paper's G mj/rc^3) plus a linear spring and a    */
+/* radial dashpot acting on the relative motion.  The potential of a    */
+/* contact pair is that of the gravity part, continuous at rc:          */
+/*     -G mj [1/sqrt(rc^2+eps^2) + (rc^2 - r^2)/(2 (rc^2+eps^2)^(3/2))]. */
+/* A pair at r = 0 (i itself) adds nothing.                             */
+/*                                                                      */
+/* magsum[i] accumulates |term| (a scale for parity tolerances).  All   */
+/* arrays are in sorted (tree) order.                                   */
 /* ------------------------------------------------------------------ */
+typedef struct {
+    double rc, kappa, eta;          /* rc = 0: gravity branch only */
+    const double *vx, *vy, *vz;     /* velocities, needed when rc > 0 */
+} orc_contact;
+
 static void add_term(double xi, double yi, double zi, double xj, double yj, double zj, double mj,
                      double eps2, double G, double acc[5])
 {
@@ -410,15 +429,45 @@ static void add_term(double xi, double yi, double zi, double xj, double yj, doub
     acc[4] += fabs(f) * sqrt(dx * dx + dy * dy + dz * dz);
 }
 
+/* A particle source j acting on particle i: Eq. (2) with both branches. */
+static void add_particle(int64_t i, int64_t j, const double *x, const double *y, const double *z,
+                         const double *m, double eps2, double G, const orc_contact *C, double acc[5])
+{
+    if (C->rc > 0.0) {
+        double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+        double d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 <= C->rc * C->rc) {
+            if (d2 == 0.0) return;
+            double r = sqrt(d2);
+            double rce2 = C->rc * C->rc + eps2;
+            double rce = sqrt(rce2);
+            double fg = G * m[j] / (rce2 * rce);
+            double dvx = C->vx[j] - C->vx[i], dvy = C->vy[j] - C->vy[i], dvz = C->vz[j] - C->vz[i];
+            double rv = dx * dvx + dy * dvy + dz * dvz;
+            double fc = m[j] / (m[i] + m[j]) * (C->kappa * (r - C->rc) / r + C->eta * rv / d2);
+            double f = fg + fc;
+            acc[0] += f * dx;
+            acc[1] += f * dy;
+            acc[2] += f * dz;
+            acc[3] -= G * m[j] * (1.0 / rce + (C->rc * C->rc - d2) / (2.0 * rce2 * rce));
+            acc[4] += fabs(f) * r;
+            return;
+        }
+    }
+    add_term(x[i], y[i], z[i], x[j], y[j], z[j], m[j], eps2, G, acc);
+}
+
 void orc_forces(int64_t n_groups, const uint32_t *gnode, const uint32_t *begin, const uint32_t *count,
                 const double *x, const double *y, const double *z, const double *m,
                 const double *M, const double *cx, const double *cy, const double *cz,
                 const int64_t *pc_off, const uint32_t *pc_ids,
                 const int64_t *pp_off, const uint32_t *pp_ids,
                 double eps, double G,
+                const double *vx, const double *vy, const double *vz, double rc, double kappa, double eta,
                 double *ax, double *ay, double *az, double *pot, double *magsum)
 {
     double eps2 = eps * eps;
+    orc_contact C = {rc, kappa, eta, vx, vy, vz};
     #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t g = 0; g < n_groups; ++g) {
         uint32_t v = gnode[g];
@@ -427,7 +476,7 @@ void orc_forces(int64_t n_groups, const uint32_t *gnode, const uint32_t *begin, 
             for (int64_t k = pp_off[g]; k < pp_off[g + 1]; ++k) {
                 uint32_t leaf = pp_ids[k];
                 for (uint32_t j = begin[leaf]; j < begin[leaf] + count[leaf]; ++j)
-                    add_term(x[i], y[i], z[i], x[j], y[j], z[j], m[j], eps2, G, acc);
+                    add_particle(i, j, x, y, z, m, eps2, G, &C, acc);
             }
             for (int64_t k = pc_off[g]; k < pc_off[g + 1]; ++k) {
                 uint32_t c = pc_ids[k];
@@ -445,19 +494,22 @@ void orc_forces(int64_t n_groups, const uint32_t *gnode, const uint32_t *begin, 
 /* ------------------------------------------------------------------ */
 /* Direct summation: the exact force the tree approximates.  For each   */
 /* target t the sum runs over every particle j (j = t included; with    */
-/* eps > 0 it adds nothing to the acceleration).                        */
+/* eps > 0 it adds nothing to the acceleration); every pair is a        */
+/* particle pair, so the collision branch applies wherever rc > 0.      */
 /* ------------------------------------------------------------------ */
 void orc_direct(int64_t n, const double *x, const double *y, const double *z, const double *m,
                 double eps, double G, int64_t nt, const int64_t *targets,
+                const double *vx, const double *vy, const double *vz, double rc, double kappa, double eta,
                 double *ax, double *ay, double *az, double *pot)
 {
     double eps2 = eps * eps;
+    orc_contact C = {rc, kappa, eta, vx, vy, vz};
     #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t t = 0; t < nt; ++t) {
         int64_t i = targets ? targets[t] : t;
         double acc[5] = {0, 0, 0, 0, 0};
         for (int64_t j = 0; j < n; ++j)
-            add_term(x[i], y[i], z[i], x[j], y[j], z[j], m[j], eps2, G, acc);
+            add_particle(i, j, x, y, z, m, eps2, G, &C, acc);
         ax[t] = acc[0];
         ay[t] = acc[1];
         az[t] = acc[2];
