@@ -9,7 +9,8 @@
  *   bh_forces       step (3d), second half: double loop over the group's
  *                   particles and its list, with the gravity branch of
  *                   Eq. (2) softened by a Plummer eps, nodes as point
- *                   masses at their centre of mass (Sec. 5.1)
+ *                   masses at their centre of mass (Sec. 5.1); optionally
+ *                   the collision branch of Eq. (2) for particle pairs
  *   bh_step         step (4) plus the persistent interaction list of
  *                   Sec. 4.2: lists are kept for `rebuild_every` steps while
  *                   node moments are recomputed from the moved particles
@@ -86,6 +87,22 @@ typedef struct {
     int32_t criterion;     /* bh_criterion */
     double theta_min, theta_max, tau;   /* learned rule only */
     int32_t flags;         /* BH_FLAG_* bits */
+    /* Collision branch of Eq. (2) (Sec. 5.1), on when r_coll > 0.  For a
+     * particle pair with r = |r_ij| <= r_coll (decided in FP64 on the
+     * absolute positions as dx*dx + dy*dy + dz*dz <= r_coll*r_coll) the
+     * acceleration of i is
+     *   [G m_j / (r_coll^2 + eps^2)^(3/2)
+     *    + m_j/(m_i + m_j) (kappa (r - r_coll)/r + eta (r_ij . v_ij)/r^2)] r_ij,
+     * r_ij = r_j - r_i, v_ij = v_j - v_i: gravity held at its value on the
+     * contact sphere (the paper's G m_j / r_coll^3 at eps = 0), a spring and
+     * a radial dashpot.  Node (centre-of-mass) sources keep the gravity
+     * branch.  The potential of a contact pair is that of its gravity part,
+     * -G m_j [1/s + (r_coll^2 - r^2)/(2 s^3)], s = sqrt(r_coll^2 + eps^2).
+     * The dashpot reads the velocities the context holds: those given to
+     * bh_build_tree (bh_forces, which then needs non-NULL vx, vy, vz), the
+     * half-kicked ones after each drift (bh_step).  The contact terms are
+     * evaluated in FP64 in both precisions.  kappa, eta >= 0, finite. */
+    double r_coll, kappa, eta;
 } bh_params;
 
 /* bh_params.flags: replay list-reusing steps eagerly instead of from a HIP graph. */
@@ -196,7 +213,9 @@ bh_status bh_step_continue(bh_ctx *ctx, double dt, int32_t n_steps, int32_t rebu
  * j over all n particles of sys (caller order; j = i adds nothing when
  * eps > 0 and is skipped when eps = 0).  targets, ax, ay, az: device arrays
  * of n_targets entries.  Uses the context's G and eps; independent of the
- * tree.  Serves as the error judge of the approximation. */
+ * tree.  Serves as the error judge of the approximation.  With r_coll > 0
+ * every pair follows Eq. (2) with both branches (see bh_params) and sys
+ * must carry velocities. */
 bh_status bh_direct_sum(bh_ctx *ctx, const bh_system *sys, const int64_t *targets, int64_t n_targets,
                         double *ax, double *ay, double *az, void *stream);
 

@@ -229,6 +229,9 @@ void refresh_state(bh_ctx *c) {
     d.eps2 = c->P.eps * c->P.eps;
     d.G = c->P.G;
     d.central_mass = c->P.central_mass;
+    d.rc = c->P.r_coll;
+    d.kappa = c->P.kappa;
+    d.eta = c->P.eta;
 }
 
 bh_status check_params(const bh_params *p) {
@@ -240,6 +243,9 @@ bh_status check_params(const bh_params *p) {
     if (p->n_group > 65536) return BH_EINVAL;
     if (p->precision != BH_FP64 && p->precision != BH_FP32_REL) return BH_EINVAL;
     if (p->criterion != BH_OPEN_GEOMETRIC && p->criterion != BH_OPEN_LEARNED) return BH_EINVAL;
+    if (!(p->r_coll >= 0.0) || !std::isfinite(p->r_coll)) return BH_EINVAL;
+    if (!(p->kappa >= 0.0) || !std::isfinite(p->kappa)) return BH_EINVAL;
+    if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return BH_EINVAL;
     return BH_OK;
 }
 
@@ -677,6 +683,8 @@ bh_status bh_make_lists(bh_ctx *c, void *stream) {
 bh_status bh_forces(bh_ctx *c, const bh_accel *out, void *stream) {
     if (!c) return BH_EINVAL;
     if (!c->lists_valid) return fail(c, BH_ESTATE, "bh_forces: no interaction lists (call bh_make_lists)");
+    if (c->P.r_coll > 0.0 && !c->have_vel)
+        return fail(c, BH_EINVAL, "bh_forces: the collision branch needs velocities in bh_build_tree");
     hipStream_t s = (hipStream_t)stream;
     bool pot = false;
     if (out)
@@ -822,11 +830,15 @@ bh_status bh_direct_sum(bh_ctx *c, const bh_system *sys, const int64_t *targets,
     if (!c || !sys || !targets || !ax || !ay || !az) return BH_EINVAL;
     if (sys->n < 1 || !sys->x || !sys->y || !sys->z || !sys->m || n_targets < 0 || sys->n >= (1ll << 31))
         return fail(c, BH_EINVAL, "bh_direct_sum: bad system or targets");
+    const bool coll = c->P.r_coll > 0.0;
+    if (coll && (!sys->vx || !sys->vy || !sys->vz))
+        return fail(c, BH_EINVAL, "bh_direct_sum: the collision branch needs velocities");
     if (n_targets == 0) return BH_OK;
     size_t need = bhk::direct_scratch_bytes(n_targets);
     HIPCHK(c, grow(c->direct_part, need));
+    const bhk::Contact ct{c->P.r_coll, c->P.kappa, c->P.eta, sys->vx, sys->vy, sys->vz};
     bhk::direct_sum(sys->x, sys->y, sys->z, sys->m, sys->n, targets, n_targets, c->P.eps * c->P.eps, c->P.G,
-                    ax, ay, az, P<double>(c->direct_part), (hipStream_t)stream);
+                    coll ? &ct : nullptr, ax, ay, az, P<double>(c->direct_part), (hipStream_t)stream);
     HIPCHK(c, hipGetLastError());
     return BH_OK;
 }

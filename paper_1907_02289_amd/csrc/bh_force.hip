@@ -22,6 +22,18 @@
 // with massless sources), so small groups do not leave most lanes idle.
 // Partial sums are added in a fixed order, so results do not depend on
 // timing.
+//
+// Collision branch of Eq. (2) (particle sources only, when rc > 0): inside
+// the pair loop the squared distance is clamped from below at rc^2 + eps^2,
+// which is exactly the branch's gravity part (continuous at rc, so the FP32
+// clamp needs no exact decision), and each lane keeps the smallest squared
+// distance it met.  A wave in which some lane came within a bound that the
+// FP32 rounding of the relative coordinates cannot cross runs a second pass
+// over the same tile, for the candidates only: the contact decision
+// dx*dx + dy*dy + dz*dz <= rc^2 and the spring and dashpot terms are taken
+// in FP64 from the absolute positions and velocities, and summed in FP64
+// apart from the gravity sums.  Contacts are rare, so the loop keeps its
+// 13-instruction body plus a max and a min.
 #include "bh_internal.hpp"
 
 namespace {
@@ -60,18 +72,24 @@ __device__ __forceinline__ double fma_r<double>(double a, double b, double c) { 
 // the same for every lane of the wave; taking them through readfirstlane
 // keeps the loop control on the scalar unit, so the vector unit issues only
 // the pair arithmetic (every lane reads the same LDS entry: a broadcast).
-template <typename R, bool POT, bool ZERO_EPS>
+// CLAMP (particle sources with the collision branch on): r^2 + eps^2 is
+// raised to at least rce2 = rc^2 + eps^2 and its smallest value kept in cmin.
+template <typename R, bool POT, bool ZERO_EPS, bool CLAMP>
 __device__ __forceinline__ void interact(const typename V4<R>::T *tile, int j0, int j1, R xi, R yi, R zi, R eps2,
-                                         R &ax, R &ay, R &az, R &pot) {
+                                         R rce2, R &ax, R &ay, R &az, R &pot, R &cmin) {
     j0 = __builtin_amdgcn_readfirstlane(j0);
     j1 = __builtin_amdgcn_readfirstlane(j1);
 #pragma unroll 8
     for (int j = j0; j < j1; ++j) {
         const typename V4<R>::T s = tile[j];
         const R dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-        const R r2 = fma_r<R>(dx, dx, fma_r<R>(dy, dy, fma_r<R>(dz, dz, eps2)));
+        R r2 = fma_r<R>(dx, dx, fma_r<R>(dy, dy, fma_r<R>(dz, dz, eps2)));
+        if (CLAMP) {
+            cmin = fmin(cmin, r2);
+            r2 = fmax(r2, rce2);
+        }
         R ri = rsqrt_r<R>(r2);
-        if (ZERO_EPS) ri = (r2 > (R)0) ? ri : (R)0;
+        if (ZERO_EPS && !CLAMP) ri = (r2 > (R)0) ? ri : (R)0;
         const R mri = s.w * ri;
         const R f = mri * (ri * ri);
         ax = fma_r<R>(f, dx, ax);
@@ -83,18 +101,22 @@ __device__ __forceinline__ void interact(const typename V4<R>::T *tile, int j0, 
 
 // The same pass when the lanes of a wave work on different source ranges
 // (sub-slices of a small group): lane base jb, common length L.
-template <typename R, bool POT, bool ZERO_EPS>
+template <typename R, bool POT, bool ZERO_EPS, bool CLAMP>
 __device__ __forceinline__ void interact_lanes(const typename V4<R>::T *tile, int jb, int L, R xi, R yi, R zi,
-                                               R eps2, R &ax, R &ay, R &az, R &pot) {
+                                               R eps2, R rce2, R &ax, R &ay, R &az, R &pot, R &cmin) {
     L = __builtin_amdgcn_readfirstlane(L);
     const typename V4<R>::T *t = tile + jb;
 #pragma unroll 8
     for (int k = 0; k < L; ++k) {
         const typename V4<R>::T s = t[k];
         const R dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-        const R r2 = fma_r<R>(dx, dx, fma_r<R>(dy, dy, fma_r<R>(dz, dz, eps2)));
+        R r2 = fma_r<R>(dx, dx, fma_r<R>(dy, dy, fma_r<R>(dz, dz, eps2)));
+        if (CLAMP) {
+            cmin = fmin(cmin, r2);
+            r2 = fmax(r2, rce2);
+        }
         R ri = rsqrt_r<R>(r2);
-        if (ZERO_EPS) ri = (r2 > (R)0) ? ri : (R)0;
+        if (ZERO_EPS && !CLAMP) ri = (r2 > (R)0) ? ri : (R)0;
         const R mri = s.w * ri;
         const R f = mri * (ri * ri);
         ax = fma_r<R>(f, dx, ax);
@@ -104,16 +126,67 @@ __device__ __forceinline__ void interact_lanes(const typename V4<R>::T *tile, in
     }
 }
 
+// Contact terms of Eq. (2) for the pair (i, j), both sorted indices, in
+// FP64 from the absolute positions and velocities: the decision
+// dx*dx + dy*dy + dz*dz <= rc^2, then spring, dashpot and the potential of the
+// gravity part inside the contact sphere, added to the thread's FP64 sums
+// c[0], c[FT], c[2 FT], c[3 FT] (x, y, z, potential) in LDS.  Values are
+// loaded only as far as the decision needs them: contacts are rare.
+template <bool POT>
+__device__ __forceinline__ void contact_term(uint32_t i, uint32_t j, const DevState &d, double *c) {
+    const double4 p = d.pos[i];
+    const double4 q = d.pos[j];
+    const double ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
+    const double d2 = ex * ex + ey * ey + ez * ez;
+    const double rc2 = d.rc * d.rc;
+    if (d2 == 0.0) {
+        // i itself (or a coincident particle): no term at all; take back the
+        // potential the pair loop added at the clamped distance
+        if (POT) c[3 * FT] += d.G * q.w / sqrt(rc2 + d.eps2);
+        return;
+    }
+    if (!(d2 <= rc2)) return;
+    const double4 vi = d.vel[i];
+    const double4 vj = d.vel[j];
+    const double r = sqrt(d2);
+    const double rv = ex * (vj.x - vi.x) + ey * (vj.y - vi.y) + ez * (vj.z - vi.z);
+    const double fc = q.w / (p.w + q.w) * (d.kappa * (r - d.rc) / r + d.eta * rv / d2);
+    c[0 * FT] += fc * ex;
+    c[1 * FT] += fc * ey;
+    c[2 * FT] += fc * ez;
+    if (POT) {
+        const double rce2 = rc2 + d.eps2;
+        c[3 * FT] -= d.G * q.w * ((rc2 - d2) / (2.0 * rce2 * sqrt(rce2)));
+    }
+}
+
+// The contact candidates of one lane's particle i among tile entries
+// [jb, jb + L): entries whose FP32 squared distance (the pair loop's own
+// expression) is within rcd2, a bound that rounding of the relative
+// coordinates cannot cross.  jidx holds the sorted index of each entry.
+template <typename R, bool POT>
+__device__ __forceinline__ void contact_pass(const typename V4<R>::T *tile, const uint32_t *jidx, int jb, int L,
+                                             R xi, R yi, R zi, R eps2, R rcd2, bool on, uint32_t i,
+                                             const DevState &d, double *c) {
+    if (!on) return;
+    for (int k = 0; k < L; ++k) {
+        const typename V4<R>::T s = tile[jb + k];
+        const R dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+        const R r2 = fma_r<R>(dx, dx, fma_r<R>(dy, dy, fma_r<R>(dz, dz, eps2)));
+        if (r2 <= rcd2) contact_term<POT>(i, jidx[jb + k], d, c);
+    }
+}
+
 // FP32: registers capped so that 6 workgroups (24 waves) fit a CU; the
 // pair loop needs the occupancy to hide LDS and rsqrt latency (measured:
 // 100 VGPRs / 4 waves per SIMD ran 18% slower).  FP64 keeps the default.
-template <typename R>
+template <typename R, bool COLL>
 struct ForceOcc {
-    static constexpr int blocks = sizeof(R) == 4 ? 6 : 1;
+    static constexpr int blocks = sizeof(R) == 4 ? (COLL ? 5 : 6) : 1;
 };
 
-template <typename R, bool POT, bool ZERO_EPS>
-__global__ void __launch_bounds__(FT, ForceOcc<R>::blocks) k_force(DevState d, uint32_t ng) {
+template <typename R, bool POT, bool ZERO_EPS, bool COLL>
+__global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevState d, uint32_t ng) {
     using T4 = typename V4<R>::T;
     __shared__ T4 tile[TJ + 16];
     __shared__ uint32_t lbeg[TJ];
@@ -121,11 +194,17 @@ __global__ void __launch_bounds__(FT, ForceOcc<R>::blocks) k_force(DevState d, u
     __shared__ R red[4][4][64];
     __shared__ uint32_t s_item;
     __shared__ uint32_t wsum[4];
+    __shared__ uint32_t jidx[COLL ? TJ : 1];            // sorted index of each particle-tile entry
+    __shared__ double cacc[COLL ? 4 : 1][COLL ? FT : 1];  // per-thread FP64 contact sums
 
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int lane = __lane_id();
     const R eps2 = (R)d.eps2;
+    const R rce2 = (R)(d.rc * d.rc + d.eps2);
+    // detection margin: a bound on how far FP32 (FP64) rounding of the
+    // group-relative coordinates can move a squared distance
+    constexpr double U = sizeof(R) == 4 ? 0x1p-20 : 0x1p-49;
 
     for (;;) {
         if (tid == 0) s_item = atomicAdd(&d.cnt->work_counter2, 1u);
@@ -165,22 +244,60 @@ __global__ void __launch_bounds__(FT, ForceOcc<R>::blocks) k_force(DevState d, u
                 zi = (R)(p.z - cen.z);
             }
             R ax = 0, ay = 0, az = 0, pot = 0;
+            R rcd2 = 0, cmin = 0;
+            if (COLL) {
+                const double n1 = fabs((double)xi) + fabs((double)yi) + fabs((double)zi);
+                const double rcd = d.rc * (1.0 + U) + 0.5 * U * n1;
+                rcd2 = (R)((rcd * rcd) * (1.0 + U) + d.eps2 * (1.0 + U));
+#pragma unroll
+                for (int a = 0; a < 4; ++a) cacc[a][tid] = 0.0;
+            }
 
             // The staged tile holds cntt sources: pad it with massless far
             // sources to a whole number of sub-slices, then let every active
             // wave (or sub-slice) run over its share.
-            auto compute_tile = [&](uint32_t cntt) {
+            // particles: whether the tile holds particle sources (the only
+            // ones the collision branch applies to)
+            auto compute_tile = [&](uint32_t cntt, bool particles) {
                 const int L = ((int)cntt + nslices - 1) / nslices;
                 if (cw < 64)
                     for (int t = (int)cntt + tid; t < L * nslices; t += FT)
                         tile[t] = mk4<R>((R)1e18, (R)1e18, (R)1e18, (R)0);
                 __syncthreads();
                 if (wave_on) {
-                    if (cw == 64) {
-                        const int j0 = (int)(cntt * jslice / split), j1 = (int)(cntt * (jslice + 1) / split);
-                        interact<R, POT, ZERO_EPS>(tile, j0, j1, xi, yi, zi, eps2, ax, ay, az, pot);
-                    } else {
-                        interact_lanes<R, POT, ZERO_EPS>(tile, slice * L, L, xi, yi, zi, eps2, ax, ay, az, pot);
+                    bool plain = true;
+                    if constexpr (COLL) {
+                        if (particles) {
+                            plain = false;
+                            int jb, jl;
+                            if (cw == 64) {
+                                jb = (int)(cntt * jslice / split);
+                                jl = (int)(cntt * (jslice + 1) / split) - jb;
+                            } else {
+                                jb = slice * L;
+                                jl = L;
+                            }
+                            cmin = (R)1e30;
+                            if (cw == 64)
+                                interact<R, POT, ZERO_EPS, true>(tile, jb, jb + jl, xi, yi, zi, eps2, rce2, ax, ay,
+                                                                 az, pot, cmin);
+                            else
+                                interact_lanes<R, POT, ZERO_EPS, true>(tile, jb, jl, xi, yi, zi, eps2, rce2, ax,
+                                                                       ay, az, pot, cmin);
+                            if (__ballot(ion && cmin <= rcd2) != 0)
+                                contact_pass<R, POT>(tile, jidx, jb, jl, xi, yi, zi, eps2, rcd2, ion, i, d,
+                                                     &cacc[0][tid]);
+                        }
+                    }
+                    if (plain) {
+                        if (cw == 64) {
+                            const int j0 = (int)(cntt * jslice / split), j1 = (int)(cntt * (jslice + 1) / split);
+                            interact<R, POT, ZERO_EPS, false>(tile, j0, j1, xi, yi, zi, eps2, rce2, ax, ay, az, pot,
+                                                              cmin);
+                        } else {
+                            interact_lanes<R, POT, ZERO_EPS, false>(tile, slice * L, L, xi, yi, zi, eps2, rce2, ax,
+                                                                    ay, az, pot, cmin);
+                        }
                     }
                 }
                 __syncthreads();
@@ -193,7 +310,7 @@ __global__ void __launch_bounds__(FT, ForceOcc<R>::blocks) k_force(DevState d, u
                     const double4 m = d.nd_mom[d.pc_pool[pc0 + t0 + tid]];
                     tile[tid] = mk4<R>((R)(m.x - cen.x), (R)(m.y - cen.y), (R)(m.z - cen.z), (R)m.w);
                 }
-                compute_tile(cntt);
+                compute_tile(cntt, false);
             }
 
             // ---- particle list: the particles of each listed leaf
@@ -227,10 +344,12 @@ __global__ void __launch_bounds__(FT, ForceOcc<R>::blocks) k_force(DevState d, u
                             const uint32_t mid = (lo + hi + 1) >> 1;
                             if (lscan[mid] <= f) lo = mid; else hi = mid - 1;
                         }
-                        const double4 q = d.pos[lbeg[lo] + (f - lscan[lo])];
+                        const uint32_t j = lbeg[lo] + (f - lscan[lo]);
+                        const double4 q = d.pos[j];
                         tile[tid] = mk4<R>((R)(q.x - cen.x), (R)(q.y - cen.y), (R)(q.z - cen.z), (R)q.w);
+                        if (COLL) jidx[tid] = j;
                     }
-                    compute_tile(cntt);
+                    compute_tile(cntt, true);
                 }
             }
 
@@ -270,7 +389,24 @@ __global__ void __launch_bounds__(FT, ForceOcc<R>::blocks) k_force(DevState d, u
                     gy += f * p.y;
                     gz += f * p.z;
                 }
-                d.acc[i] = make_double4(gx, gy, gz, POT ? d.G * (double)sp : 0.0);
+                double gp = POT ? d.G * (double)sp : 0.0;
+                if (COLL) {
+                    // contact sums of the threads that worked on particle i, in a fixed order
+                    double cx = 0, cy = 0, cz = 0, cp = 0;
+                    for (int k = 0; k < split; ++k)
+                        for (int sb = 0; sb < sub; ++sb) {
+                            const int th = (k * n_ic + ichunk) * 64 + sb * cw + lane;
+                            cx += cacc[0][th];
+                            cy += cacc[1][th];
+                            cz += cacc[2][th];
+                            cp += cacc[3][th];
+                        }
+                    gx += cx;
+                    gy += cy;
+                    gz += cz;
+                    gp += cp;
+                }
+                d.acc[i] = make_double4(gx, gy, gz, POT ? gp : 0.0);
             }
             __syncthreads();
         }
@@ -283,10 +419,16 @@ __global__ void k_force_reset(DevState d) {
 
 template <typename R, bool POT>
 void launch(const DevState &d, uint32_t ng, int blocks, hipStream_t s) {
-    if (d.eps2 == 0.0)
-        k_force<R, POT, true><<<blocks, FT, 0, s>>>(d, ng);
-    else
-        k_force<R, POT, false><<<blocks, FT, 0, s>>>(d, ng);
+    if (d.rc > 0.0) {
+        if (d.eps2 == 0.0)
+            k_force<R, POT, true, true><<<blocks, FT, 0, s>>>(d, ng);
+        else
+            k_force<R, POT, false, true><<<blocks, FT, 0, s>>>(d, ng);
+    } else if (d.eps2 == 0.0) {
+        k_force<R, POT, true, false><<<blocks, FT, 0, s>>>(d, ng);
+    } else {
+        k_force<R, POT, false, false><<<blocks, FT, 0, s>>>(d, ng);
+    }
 }
 
 }  // namespace

@@ -181,6 +181,7 @@ struct DevState {
     int n_leaf, n_grp;
     double th2;                    // theta * theta
     double eps2, G, central_mass;
+    double rc, kappa, eta;         // collision branch of Eq. (2); rc = 0: off
 };
 
 enum { WALK_GEOMETRIC = 0, WALK_LEARNED = 1, WALK_ENUMERATE = 2 };
@@ -230,10 +231,16 @@ void mlp_eval(const float *w, const float4 *X, uint64_t n, float *out, hipStream
 void perm_keys(uint64_t *key, uint32_t *val, uint64_t n, uint64_t seed, hipStream_t s);
 
 // FP64 direct summation for sampled targets (bh_direct.hip)
+// Collision branch of Eq. (2) for the direct sum: radius, spring, dashpot and
+// the caller-order velocities of the system.
+struct Contact {
+    double rc, kappa, eta;
+    const double *vx, *vy, *vz;
+};
 size_t direct_scratch_bytes(int64_t n_targets);
 void direct_sum(const double *x, const double *y, const double *z, const double *m, int64_t n,
-                const int64_t *targets, int64_t nt, double eps2, double G, double *ax, double *ay, double *az,
-                double *scratch, hipStream_t s);
+                const int64_t *targets, int64_t nt, double eps2, double G, const Contact *contact, double *ax,
+                double *ay, double *az, double *scratch, hipStream_t s);
 
 // exclusive scan of n uint32 (n from *n_dev when n_dev != nullptr, else n_host);
 // out may alias in.  *total (if non-null) receives the sum.  tmp: >= 1024 words.
