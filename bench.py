@@ -17,6 +17,9 @@ library's FP64 direct sum) is at most 1e-3:
   plain: FP64 interactions, groups <= 64, lists rebuilt every step.
 The JSON line reports the tuned path's interactions/s (whole job, inputs
 resident in device memory) and, alongside, the plain path and the oracle.
+The "collisions" object times the tuned path again with the collision branch
+of Eq. (2) on: particle radius from an optical depth of 0.5 over the ring's
+area, r_coll = 2 radii, contact time 32 steps, restitution 0.5.
 """
 import argparse
 import hashlib
@@ -125,6 +128,23 @@ def learned_path(bh, inputs, w, dev0, sample, ref, n, tuned, args):
     return p
 
 
+def collision_params(w, tau_opt=0.5, steps_per_contact=32, restitution=0.5):
+    """Collision radius, spring and dashpot for the benchmark ring: equal
+    particles of radius a with N pi a^2 = tau_opt * ring area, r_coll = 2a;
+    kappa, eta of the damped oscillator (the relative motion of a contact)
+    that lasts steps_per_contact steps and returns `restitution` of the
+    approach speed."""
+    s = w.systems[0]
+    r_cyl = np.hypot(s.x, s.y)
+    area = math.pi * (r_cyl.max() ** 2 - r_cyl.min() ** 2)
+    a = math.sqrt(tau_opt * area / (math.pi * s.n))
+    t_c = steps_per_contact * w.dt
+    wd = math.pi / t_c
+    gamma = -math.log(restitution) / t_c
+    return dict(r_coll=2.0 * a, kappa=wd * wd + gamma * gamma, eta=2.0 * gamma), dict(
+        optical_depth=tau_opt, t_contact=t_c, restitution=restitution)
+
+
 def force_source_digest():
     src = os.path.join(ROOT, "paper_1907_02289_amd", "csrc", "bh_force.hip")
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -205,6 +225,7 @@ def main():
     ap.add_argument("--theta-tuned", type=float, default=None, help="skip tuning, use this theta (tuned path)")
     ap.add_argument("--theta-plain", type=float, default=None, help="skip tuning, use this theta (plain path)")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
+    ap.add_argument("--no-collisions", action="store_true", help="skip timing the collision branch")
     ap.add_argument("--learned", action="store_true",
                     help="also train, tune and time the learned-criterion form (off by default: see the design notes)")
     args = ap.parse_args()
@@ -275,7 +296,7 @@ def main():
     def timed(p, steps, warmup, leap_per_step):
         dev = {k: v.clone() for k, v in dev0.items()}
         ctx = bh.Context(theta=p["theta"], eps=w.eps, central_mass=w.central_mass, precision=p["precision"],
-                         n_group=p["n_group"], **p.get("learned", {}))
+                         n_group=p["n_group"], **p.get("learned", {}), **p.get("contact", {}))
         if "weights" in p:
             ctx.mlp_weights(set=p["weights"])
         ctx.step([dev], w.dt, 0, p["rebuild_every"])
@@ -309,6 +330,12 @@ def main():
         log(f"[bench] learned: {lr}")
     pl = timed(paths["plain"], args.plain_steps, 1, 1)
     log(f"[bench] plain: {pl}")
+    co = None
+    if not args.no_collisions:
+        cparams, cinfo = collision_params(w)
+        co_steps = max(2, args.steps // 2)
+        co = timed(dict(paths["tuned"], contact=cparams), co_steps, 1, R)
+        log(f"[bench] collisions {cparams}: {co}")
 
     leap_t = tu["wall"] / (args.steps * R)
     leap_p = pl["wall"] / args.plain_steps
@@ -352,6 +379,15 @@ def main():
                      / FP32_PEAK_TFLOPS},
         "stages_ms_last": tu["stages"],
     }
+    if co is not None:
+        c_launch = co["interactions"] / max(1, co["force_evals"])
+        c_ms = co["force_ms"] / max(1, co["force_launches"])
+        c_ach = c_launch * FLOPS_PER_INTERACTION / (c_ms * 1e-3) / 1e12
+        out["collisions"] = dict(cparams, **cinfo, s_per_step=co["wall"] / (co_steps * R),
+                                 interactions_per_s=co["interactions"] / co["wall"],
+                                 interactions_per_force_eval=c_launch, force_kernel_ms=c_ms,
+                                 force_kernel_ms_ratio_vs_gravity_only=c_ms / avg_ms,
+                                 achieved_tflops_19=c_ach, frac=c_ach / FP32_PEAK_TFLOPS)
     if lr is not None:
         lps = lr["wall"] / (max(1, args.steps // 2) * R)
         out["learned"] = {"s_per_step": lps, "interactions_per_s": lr["interactions"] / lr["wall"],
@@ -362,7 +398,7 @@ def main():
                           "interactions_vs_geometric": (lr["interactions"] / max(1, lr["force_evals"])) / per_launch}
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(sysm, paths["tuned"]["theta"], args.n_group, w.eps, R)
+        out["cpu_baseline"] = cpu_baseline(sysm, paths["tuned"]["theta"], paths["tuned"]["n_group"], w.eps, R)
     print(json.dumps(out), flush=True)
 
 

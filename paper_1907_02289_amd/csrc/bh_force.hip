@@ -32,8 +32,10 @@
 // over the same tile, for the candidates only: the contact decision
 // dx*dx + dy*dy + dz*dz <= rc^2 and the spring and dashpot terms are taken
 // in FP64 from the absolute positions and velocities, and summed in FP64
-// apart from the gravity sums.  Contacts are rare, so the loop keeps its
-// 13-instruction body plus a max and a min.
+// apart from the gravity sums.  The clamped loop (the 13-instruction body
+// plus a max and a min) runs only on tiles whose bounding box comes within
+// that bound of some particle of the wave; every other tile takes the plain
+// loop, which is then exact because no pair in it can reach the clamp.
 #include "bh_internal.hpp"
 
 namespace {
@@ -195,6 +197,7 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
     __shared__ uint32_t s_item;
     __shared__ uint32_t wsum[4];
     __shared__ uint32_t jidx[COLL ? TJ : 1];            // sorted index of each particle-tile entry
+    __shared__ R tbox[COLL ? 4 : 1][6];                  // per-wave bounds of a particle tile
     __shared__ double cacc[COLL ? 4 : 1][COLL ? FT : 1];  // per-thread FP64 contact sums
 
     const int tid = threadIdx.x;
@@ -267,7 +270,25 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                 if (wave_on) {
                     bool plain = true;
                     if constexpr (COLL) {
+                        // is any particle of the wave near the tile's bounding box?  The
+                        // gaps bound every pair's rounded distance from below (rounding
+                        // is monotone), so a wave with none near cannot meet the clamp.
+                        bool near = false;
                         if (particles) {
+                            R b[6];
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                b[a] = fmin(fmin(tbox[0][a], tbox[1][a]), fmin(tbox[2][a], tbox[3][a]));
+                                b[a + 3] = fmax(fmax(tbox[0][a + 3], tbox[1][a + 3]),
+                                                fmax(tbox[2][a + 3], tbox[3][a + 3]));
+                            }
+                            const R gx = fmax((R)0, fmax(b[0] - xi, xi - b[3]));
+                            const R gy = fmax((R)0, fmax(b[1] - yi, yi - b[4]));
+                            const R gz = fmax((R)0, fmax(b[2] - zi, zi - b[5]));
+                            const R g2 = fma_r<R>(gx, gx, fma_r<R>(gy, gy, fma_r<R>(gz, gz, eps2)));
+                            near = __ballot(ion && g2 <= rcd2) != 0;
+                        }
+                        if (near) {
                             plain = false;
                             int jb, jl;
                             if (cw == 64) {
@@ -337,6 +358,7 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                 __syncthreads();
                 for (uint32_t p0 = 0; p0 < tot; p0 += TJ) {
                     const uint32_t cntt = min((uint32_t)TJ, tot - p0);
+                    T4 e = mk4<R>((R)0, (R)0, (R)0, (R)0);
                     if ((uint32_t)tid < cntt) {
                         const uint32_t f = p0 + tid;
                         uint32_t lo = 0, hi = nl - 1;          // last k with lscan[k] <= f
@@ -346,8 +368,26 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                         }
                         const uint32_t j = lbeg[lo] + (f - lscan[lo]);
                         const double4 q = d.pos[j];
-                        tile[tid] = mk4<R>((R)(q.x - cen.x), (R)(q.y - cen.y), (R)(q.z - cen.z), (R)q.w);
+                        e = mk4<R>((R)(q.x - cen.x), (R)(q.y - cen.y), (R)(q.z - cen.z), (R)q.w);
+                        tile[tid] = e;
                         if (COLL) jidx[tid] = j;
+                    }
+                    if constexpr (COLL) {
+                        // bounding box of the tile's entries, per wave
+                        const bool has = (uint32_t)tid < cntt;
+                        const R big = (R)1e30;
+                        const R lx = wave_min(has ? e.x : big), ly = wave_min(has ? e.y : big),
+                                lz = wave_min(has ? e.z : big);
+                        const R hx = wave_max(has ? e.x : -big), hy = wave_max(has ? e.y : -big),
+                                hz = wave_max(has ? e.z : -big);
+                        if (lane == 0) {
+                            tbox[w][0] = lx;
+                            tbox[w][1] = ly;
+                            tbox[w][2] = lz;
+                            tbox[w][3] = hx;
+                            tbox[w][4] = hy;
+                            tbox[w][5] = hz;
+                        }
                     }
                     compute_tile(cntt, true);
                 }
