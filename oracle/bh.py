@@ -21,7 +21,7 @@ __all__ = [
     "lib", "keys", "sort_perm", "tree", "moments", "groups", "group_boxes",
     "lists", "forces", "direct", "central", "bh_accel", "direct_accel",
     "kdk", "n_threads", "BHState", "lg2p", "node_qn", "box_ratio2", "features", "mlp_forward", "lists_learned",
-    "label_ratio",
+    "label_ratio", "keys_cyl", "atan2", "CYL_PERIOD",
 ]
 
 _lib = None
@@ -46,6 +46,11 @@ def lib():
         L.orc_groups.restype = i64
         L.orc_group_boxes.argtypes = [i64, P, P, P, P, P, P, P, P, P]
         L.orc_lists.argtypes = [i64, P, P, P, P, P, dbl, P, P, P, P]
+        L.orc_lists_p.argtypes = [i64, P, P, P, P, P, dbl, i64, P, P, P, P]
+        L.orc_keys_cyl.argtypes = [i64, P, P, P, dbl, P, P, P, P]
+        L.orc_keys_cyl.restype = C.c_int
+        L.orc_atan2.argtypes = [dbl, dbl]
+        L.orc_atan2.restype = dbl
         L.orc_forces.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, dbl, dbl, P, P, P, dbl, dbl, dbl,
                                  P, P, P, P, P]
         L.orc_direct.argtypes = [i64, P, P, P, P, dbl, dbl, i64, P, P, P, P, dbl, dbl, dbl, P, P, P, P]
@@ -90,6 +95,31 @@ def keys(x, y, z):
     rc = lib().orc_keys(n, _p(x), _p(y), _p(z), _p(lo), _p(S), _p(q), _p(k))
     if rc != 0:
         raise ValueError("oracle keys: non-finite coordinate or empty input")
+    return lo, float(S[0]), q, k
+
+
+CYL_PERIOD = 1 << 21      # grid units of one turn in phi (cylindrical tree coordinates)
+
+
+def atan2(y, x):
+    """The oracle's angle of (x, y), from correctly rounded operations only."""
+    return float(lib().orc_atan2(float(y), float(x)))
+
+
+def keys_cyl(x, y, z, r_ref):
+    """Keys on cylindrical tree coordinates (phi, r, z) for a ring near radius
+    r_ref: returns (lo[3] = (-pi, min r, min z), S = 2 pi r_ref, q[n,3], key)."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    n = x.size
+    lo = np.zeros(3)
+    S = np.zeros(1)
+    q = np.zeros((n, 3), np.uint32)
+    k = np.zeros(n, np.uint64)
+    rc = lib().orc_keys_cyl(n, _p(x), _p(y), _p(z), float(r_ref), _p(lo), _p(S), _p(q), _p(k))
+    if rc == -2:
+        raise ValueError("oracle keys_cyl: radial or vertical extent exceeds 2 pi r_ref")
+    if rc != 0:
+        raise ValueError("oracle keys_cyl: non-finite coordinate, empty input or r_ref <= 0")
     return lo, float(S[0]), q, k
 
 
@@ -147,18 +177,19 @@ def group_boxes(gnode, t, skey, xs, ys, zs):
     return gbox, gcen
 
 
-def lists(gbox, t, theta):
+def lists(gbox, t, theta, period=0):
+    """Interaction lists; period > 0 makes the first grid axis periodic."""
     gbox = np.ascontiguousarray(gbox, np.int32)
     ng = gbox.shape[0]
     pc_off = np.zeros(ng + 1, np.int64)
     pp_off = np.zeros(ng + 1, np.int64)
     L = lib()
     args = (_p(gbox), _p(t["level"]), _p(t["prefix"]), _p(t["first_child"]), _p(t["n_child"]),
-            float(theta))
-    L.orc_lists(ng, *args, _p(pc_off), _p(pp_off), None, None)
+            float(theta), int(period))
+    L.orc_lists_p(ng, *args, _p(pc_off), _p(pp_off), None, None)
     pc = np.zeros(max(1, int(pc_off[-1])), np.uint32)
     pp = np.zeros(max(1, int(pp_off[-1])), np.uint32)
-    L.orc_lists(ng, *args, _p(pc_off), _p(pp_off), _p(pc), _p(pp))
+    L.orc_lists_p(ng, *args, _p(pc_off), _p(pp_off), _p(pc), _p(pp))
     return pc_off, pc[: pc_off[-1]].copy(), pp_off, pp[: pp_off[-1]].copy()
 
 
@@ -215,8 +246,11 @@ def central(x, y, z, Mc, G, ax, ay, az):
 class BHState:
     """Tree, groups and lists of one build, kept for list-reusing steps."""
 
-    def __init__(self, x, y, z, m, theta, n_leaf, n_grp, with_q=False):
-        self.lo, self.S, _, key = keys(x, y, z)
+    def __init__(self, x, y, z, m, theta, n_leaf, n_grp, with_q=False, cyl_r=0.0):
+        if cyl_r > 0.0:
+            self.lo, self.S, _, key = keys_cyl(x, y, z, cyl_r)
+        else:
+            self.lo, self.S, _, key = keys(x, y, z)
         self.perm = sort_perm(key)
         self.skey = key[self.perm]
         self.tree = tree(self.skey, n_leaf)
@@ -224,7 +258,8 @@ class BHState:
         self.mom = moments(self.tree, xs, ys, zs, ms, with_q)
         self.gnode = groups(self.tree, n_grp)
         self.gbox, self.gcen = group_boxes(self.gnode, self.tree, self.skey, xs, ys, zs)
-        self.pc_off, self.pc, self.pp_off, self.pp = lists(self.gbox, self.tree, theta)
+        self.pc_off, self.pc, self.pp_off, self.pp = lists(self.gbox, self.tree, theta,
+                                                           CYL_PERIOD if cyl_r > 0.0 else 0)
 
     def refresh(self, x, y, z, m):
         """List-reusing step: same topology, moments from the current positions."""
@@ -251,9 +286,9 @@ class BHState:
         return int(np.sum(ng * (pp_len + pc_len)))
 
 
-def bh_accel(x, y, z, m, theta, eps, n_leaf=8, n_grp=64, G=1.0, vel=None, contact=None):
+def bh_accel(x, y, z, m, theta, eps, n_leaf=8, n_grp=64, G=1.0, vel=None, contact=None, cyl_r=0.0):
     """Full Barnes-Hut force in caller order: (ax, ay, az, pot, magsum, state)."""
-    st = BHState(x, y, z, m, theta, n_leaf, n_grp)
+    st = BHState(x, y, z, m, theta, n_leaf, n_grp, cyl_r=cyl_r)
     return (*st.accel(x, y, z, m, eps, G, vel, contact), st)
 
 

@@ -119,6 +119,110 @@ int orc_keys(int64_t n, const double *x, const double *y, const double *z,
 }
 
 /* ------------------------------------------------------------------ */
+/* Cylindrical tree coordinates (Sec. 4.3, Eq. (1)): for a narrow ring  */
+/* near radius r_ref the arc r_ref*phi, the radius r and the height z   */
+/* are locally Cartesian, so the tree (keys, cells, groups, opening     */
+/* test) is built on them while the forces stay Cartesian.  Reading:    */
+/*   phi = the angle of (x, y) in [-pi, pi], r = sqrt(x*x + y*y);       */
+/*   the root cell has side S = 2 pi r_ref, its phi axis spans exactly  */
+/*   one turn, [-pi, pi) -> [0, 2^21) with q = floor((phi + pi) 2^21 /  */
+/*   (2 pi)), and r, z use q = floor((v - min v) 2^21 / S); all q are   */
+/*   clamped to 2^21 - 1.  The phi axis is periodic (period 2^21 grid   */
+/*   units), which the opening test takes into account.                 */
+/* The angle comes from orc_atan2 below, built from correctly rounded   */
+/* operations only, so that any implementation of the same steps gets   */
+/* the same bits.                                                        */
+/* ------------------------------------------------------------------ */
+#define ORC_PI 3.141592653589793
+#define ORC_TAN_PI8 0.41421356237309503     /* tan(pi/8) = sqrt(2) - 1 */
+#define ORC_ATAN_TERMS 15                   /* t, t^3, ..., t^29 */
+
+/* arctan(t) for |t| <= tan(pi/8): the Maclaurin series
+ *   t - t^3/3 + t^5/5 - ... (Abramowitz & Stegun 4.4.42)
+ * up to t^29, by Horner's rule in t^2 from the highest term down; the
+ * coefficients are (-1)^k / (2k+1), each one correctly rounded division.
+ * Truncation error below |t|^31/31 < 2e-14. */
+static double atan_series(double t)
+{
+    double t2 = t * t;
+    double p = 0.0;
+    for (int k = ORC_ATAN_TERMS - 1; k >= 0; --k) {
+        double c = 1.0 / (double)(2 * k + 1);
+        if (k & 1) c = -c;
+        p = p * t2 + c;
+    }
+    return t * p;
+}
+
+/* The angle of (x, y) in [-pi, pi]: reduce to t = min/max(|x|,|y|) in
+ * [0, 1]; above tan(pi/8) use arctan t = pi/4 + arctan((t-1)/(t+1))
+ * (the addition formula, A&S 4.4.34); then reflect into the octant and
+ * quadrant of (x, y).  (0, 0) gives 0. */
+double orc_atan2(double y, double x)
+{
+    double ax = fabs(x), ay = fabs(y);
+    if (ax == 0.0 && ay == 0.0) return 0.0;
+    int swap = ay > ax;
+    double t = swap ? ax / ay : ay / ax;
+    double a;
+    if (t > ORC_TAN_PI8)
+        a = 0.25 * ORC_PI + atan_series((t - 1.0) / (t + 1.0));
+    else
+        a = atan_series(t);
+    if (swap) a = 0.5 * ORC_PI - a;
+    if (x < 0.0) a = ORC_PI - a;
+    if (y < 0.0) a = -a;
+    return a;
+}
+
+/* Returns 0; -1 for non-finite input, n < 1 or r_ref <= 0; -2 when the  */
+/* radial or vertical extent does not fit the root cell.                 */
+int orc_keys_cyl(int64_t n, const double *x, const double *y, const double *z, double r_ref,
+                 double *lo3, double *S_out, uint32_t *q3, uint64_t *key)
+{
+    if (n < 1 || !(r_ref > 0.0) || !isfinite(r_ref)) return -1;
+    double *phi = (double *)malloc((size_t)n * sizeof(double));
+    double *rad = (double *)malloc((size_t)n * sizeof(double));
+    double rlo = 0, rhi = 0, zlo = 0, zhi = 0;
+    int bad = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!isfinite(x[i]) || !isfinite(y[i]) || !isfinite(z[i])) bad = 1;
+        phi[i] = orc_atan2(y[i], x[i]);
+        rad[i] = sqrt(x[i] * x[i] + y[i] * y[i]);
+        if (i == 0 || rad[i] < rlo) rlo = rad[i];
+        if (i == 0 || rad[i] > rhi) rhi = rad[i];
+        if (i == 0 || z[i] < zlo) zlo = z[i];
+        if (i == 0 || z[i] > zhi) zhi = z[i];
+    }
+    double S = (2.0 * ORC_PI) * r_ref;
+    int rc = bad ? -1 : ((rhi - rlo >= S || zhi - zlo >= S) ? -2 : 0);
+    if (rc == 0) {
+        double kphi = 2097152.0 / (2.0 * ORC_PI), k = 2097152.0 / S;
+        lo3[0] = -ORC_PI;
+        lo3[1] = rlo;
+        lo3[2] = zlo;
+        *S_out = S;
+        for (int64_t i = 0; i < n; ++i) {
+            double t[3] = {(phi[i] + ORC_PI) * kphi, (rad[i] - rlo) * k, (z[i] - zlo) * k};
+            uint32_t q[3];
+            for (int d = 0; d < 3; ++d) {
+                double f = floor(t[d]);
+                q[d] = (f >= 2097151.0) ? 2097151u : (uint32_t)f;
+            }
+            if (q3) {
+                q3[3 * i + 0] = q[0];
+                q3[3 * i + 1] = q[1];
+                q3[3 * i + 2] = q[2];
+            }
+            key[i] = interleave3(q[0], q[1], q[2]);
+        }
+    }
+    free(phi);
+    free(rad);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* Sort (Sec. 4.2: sorting is the dominant cost of tree construction). */
 /* Ascending by (key, original index): a stable sort by key.           */
 /* ------------------------------------------------------------------ */
@@ -289,9 +393,21 @@ void orc_group_boxes(int64_t n_groups, const uint32_t *gnode, const uint32_t *be
 /* outside the group's box and s / d < theta, d being the distance from */
 /* the node's geometric centre to the nearest point of the group box.   */
 /* Computed in doubled integer grid units: the only floating-point      */
-/* operation is the multiplication by th2 = theta*theta.                */
+/* operation is the multiplication by th2 = theta*theta.  With a        */
+/* periodic first axis (cylindrical coordinates, period P grid units)   */
+/* the distance along it is that to the nearest image of the node; a    */
+/* node and a group box, both inside one period, overlap only directly. */
 /* ------------------------------------------------------------------ */
-static int accept_cell(const int32_t *gb, int lvl, uint64_t pfx, double th2)
+static int64_t axis_gap2(int64_t C, int64_t gl, int64_t gh)
+{
+    /* doubled distance from doubled centre C to the interval [gl, gh] */
+    int64_t da = 0;
+    if (2 * gl - C > da) da = 2 * gl - C;
+    if (C - 2 * gh > da) da = C - 2 * gh;
+    return da;
+}
+
+static int accept_cell_p(const int32_t *gb, int lvl, uint64_t pfx, double th2, int64_t period)
 {
     uint32_t p[3];
     deinterleave3(pfx, lvl, p);
@@ -303,13 +419,21 @@ static int accept_cell(const int32_t *gb, int lvl, uint64_t pfx, double th2)
         int64_t gl = gb[a], gh = gb[3 + a];
         if (L + s <= gl || L >= gh) disjoint = 1;
         int64_t C = 2 * L + s;
-        int64_t da = 0;
-        if (2 * gl - C > da) da = 2 * gl - C;
-        if (C - 2 * gh > da) da = C - 2 * gh;
+        int64_t da = axis_gap2(C, gl, gh);
+        if (a == 0 && period > 0) {
+            int64_t dm = axis_gap2(C - 2 * period, gl, gh), dp = axis_gap2(C + 2 * period, gl, gh);
+            if (dm < da) da = dm;
+            if (dp < da) da = dp;
+        }
         d2 += da * da;
     }
     int64_t s2 = (2 * s) * (2 * s);
     return disjoint && ((double)s2 < th2 * (double)d2);
+}
+
+static int accept_cell(const int32_t *gb, int lvl, uint64_t pfx, double th2)
+{
+    return accept_cell_p(gb, lvl, pfx, th2, 0);
 }
 
 typedef struct { uint32_t *v; int64_t n, cap; } u32vec;
@@ -330,25 +454,26 @@ static int cmp_u32(const void *a, const void *b)
 /* The traversal: an accepted node goes to the node list, a rejected    */
 /* leaf to the particle list, a rejected internal node is opened.       */
 static void walk_rec(uint32_t v, const int32_t *gb, const uint8_t *level, const uint64_t *prefix,
-                     const uint32_t *first_child, const uint8_t *n_child, double th2,
+                     const uint32_t *first_child, const uint8_t *n_child, double th2, int64_t period,
                      u32vec *pc, u32vec *pp)
 {
-    if (accept_cell(gb, level[v], prefix[v], th2)) {
+    if (accept_cell_p(gb, level[v], prefix[v], th2, period)) {
         vpush(pc, v);
     } else if (n_child[v] == 0) {
         vpush(pp, v);
     } else {
         for (int c = 0; c < n_child[v]; ++c)
-            walk_rec(first_child[v] + c, gb, level, prefix, first_child, n_child, th2, pc, pp);
+            walk_rec(first_child[v] + c, gb, level, prefix, first_child, n_child, th2, period, pc, pp);
     }
 }
 
 /* Interaction lists for every group, in canonical form (each list in  */
 /* ascending node id).  pc_off/pp_off have n_groups+1 entries.  When    */
-/* pc_ids/pp_ids are NULL only the offsets are produced.                */
-void orc_lists(int64_t n_groups, const int32_t *gbox, const uint8_t *level, const uint64_t *prefix,
-               const uint32_t *first_child, const uint8_t *n_child, double theta,
-               int64_t *pc_off, int64_t *pp_off, uint32_t *pc_ids, uint32_t *pp_ids)
+/* pc_ids/pp_ids are NULL only the offsets are produced.  period > 0:   */
+/* the first grid axis is periodic with that many grid units.           */
+void orc_lists_p(int64_t n_groups, const int32_t *gbox, const uint8_t *level, const uint64_t *prefix,
+                 const uint32_t *first_child, const uint8_t *n_child, double theta, int64_t period,
+                 int64_t *pc_off, int64_t *pp_off, uint32_t *pc_ids, uint32_t *pp_ids)
 {
     double th2 = theta * theta;
     int64_t *pcn = (int64_t *)calloc((size_t)n_groups, sizeof(int64_t));
@@ -356,7 +481,7 @@ void orc_lists(int64_t n_groups, const int32_t *gbox, const uint8_t *level, cons
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t g = 0; g < n_groups; ++g) {
         u32vec pc = {0, 0, 0}, pp = {0, 0, 0};
-        walk_rec(0, gbox + 6 * g, level, prefix, first_child, n_child, th2, &pc, &pp);
+        walk_rec(0, gbox + 6 * g, level, prefix, first_child, n_child, th2, period, &pc, &pp);
         pcn[g] = pc.n;
         ppn[g] = pp.n;
         free(pc.v);
@@ -372,7 +497,7 @@ void orc_lists(int64_t n_groups, const int32_t *gbox, const uint8_t *level, cons
         #pragma omp parallel for schedule(dynamic, 16)
         for (int64_t g = 0; g < n_groups; ++g) {
             u32vec pc = {0, 0, 0}, pp = {0, 0, 0};
-            walk_rec(0, gbox + 6 * g, level, prefix, first_child, n_child, th2, &pc, &pp);
+            walk_rec(0, gbox + 6 * g, level, prefix, first_child, n_child, th2, period, &pc, &pp);
             qsort(pc.v, (size_t)pc.n, sizeof(uint32_t), cmp_u32);
             qsort(pp.v, (size_t)pp.n, sizeof(uint32_t), cmp_u32);
             if (pc.n) memcpy(pc_ids + pc_off[g], pc.v, (size_t)pc.n * sizeof(uint32_t));
@@ -383,6 +508,13 @@ void orc_lists(int64_t n_groups, const int32_t *gbox, const uint8_t *level, cons
     }
     free(pcn);
     free(ppn);
+}
+
+void orc_lists(int64_t n_groups, const int32_t *gbox, const uint8_t *level, const uint64_t *prefix,
+               const uint32_t *first_child, const uint8_t *n_child, double theta,
+               int64_t *pc_off, int64_t *pp_off, uint32_t *pc_ids, uint32_t *pp_ids)
+{
+    orc_lists_p(n_groups, gbox, level, prefix, first_child, n_child, theta, 0, pc_off, pp_off, pc_ids, pp_ids);
 }
 
 /* ------------------------------------------------------------------ */
