@@ -124,7 +124,7 @@ def learned_path(bh, inputs, w, dev0, sample, ref, n, tuned, args):
     log(f"[bench] learned: tau=1e{lt:.3f} p99={e[0]:.3e}")
     p = dict(tuned)
     p.update(learned=dict(kw, tau=10.0 ** lt), weights=weights, p99=e[0], p50=e[1], training_pairs=n_pairs,
-             training_mse=mse)
+             training_mse=mse, tree="cartesian", cyl_radius=0.0)     # the learned rule is Cartesian only
     return p
 
 
@@ -145,21 +145,101 @@ def collision_params(w, tau_opt=0.5, steps_per_contact=32, restitution=0.5):
         optical_depth=tau_opt, t_contact=t_c, restitution=restitution)
 
 
+REUSE_INTERVALS = (1, 2, 4, 8, 16)
+
+
+def reuse_study(bh, w, dev0, sample, n, n_group, steps, cyl_radius=0.0, theta_lo=0.05, theta_hi=0.2, iters=7):
+    """Interaction-list reuse (persistent lists): for each rebuild interval R,
+    the loosest theta whose force error stays within p99 <= 1e-3 at every
+    list age 0..R-1 of a cycle (positions moved by the leapfrog, moments
+    refreshed, the judge recomputed at each age), then the time per step of
+    that configuration.  Returns one record per R."""
+    import torch
+    judge = bh.Context(theta=0.5, eps=w.eps)
+    gmc = w.central_mass * 1.0
+
+    def cycle_errors(theta, R):
+        dev = {k: v.clone() for k, v in dev0.items()}
+        ctx = bh.Context(theta=theta, eps=w.eps, central_mass=w.central_mass, precision=bh.FP32_REL,
+                         n_group=n_group, cyl_radius=cyl_radius)
+        big = 1 << 30                         # never rebuild inside the cycle
+        ctx.step([dev], w.dt, 0, big)
+        errs = []
+        for age in range(R):
+            if age:
+                ctx.step_continue(w.dt, 1, big)
+            ref = {k: torch.zeros(sample.numel(), dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+            judge.direct_sum(dev, sample, ref)
+            out = {k: torch.zeros(n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az", "pot")}
+            ctx.forces([out])
+            x, y, z = dev["x"][sample], dev["y"][sample], dev["z"][sample]
+            r3 = (x * x + y * y + z * z) ** 1.5
+            a = torch.stack([out["ax"][sample] + gmc * x / r3, out["ay"][sample] + gmc * y / r3,
+                             out["az"][sample] + gmc * z / r3])
+            r = torch.stack([ref["ax"], ref["ay"], ref["az"]])
+            e = (torch.linalg.vector_norm(a - r, dim=0) / torch.linalg.vector_norm(r, dim=0)).cpu().numpy()
+            errs.append(float(np.sort(e)[int(math.ceil(0.99 * e.size)) - 1]))
+        inter = ctx.query()["interactions"]
+        ctx.close()
+        del dev
+        return errs, inter
+
+    out = []
+    for R in REUSE_INTERVALS:
+        lo, hi, best = theta_lo, theta_hi, None
+        for _ in range(iters):
+            mid = 0.5 * (lo + hi)
+            errs, inter = cycle_errors(mid, R)
+            if max(errs) <= TARGET_P99:
+                lo, best = mid, (mid, errs, inter)
+            else:
+                hi = mid
+        if best is None:
+            errs, inter = cycle_errors(theta_lo, R)
+            best = (theta_lo, errs, inter)
+        th, errs, inter = best
+        # time `steps` cycles of this configuration
+        dev = {k: v.clone() for k, v in dev0.items()}
+        ctx = bh.Context(theta=th, eps=w.eps, central_mass=w.central_mass, precision=bh.FP32_REL, n_group=n_group,
+                         cyl_radius=cyl_radius)
+        ctx.step([dev], w.dt, 0, R)
+        ctx.step_continue(w.dt, R, R)
+        torch.cuda.synchronize()
+        n_leap = max(R, (steps * 4 // R) * R)
+        t0 = time.perf_counter()
+        ctx.step_continue(w.dt, n_leap, R)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = ctx.stage_times()
+        ctx.close()
+        del dev
+        torch.cuda.empty_cache()
+        rec = dict(rebuild_every=R, theta=th, p99_by_age=errs, interactions_per_force_eval_at_build=inter,
+                   s_per_step=wall / n_leap, leapfrog_steps_timed=n_leap,
+                   rebuild_ms=st["keys_sort"] + st["tree"] + st["moments"] + st["groups"] + st["walk"],
+                   force_ms=st["forces"])
+        log(f"[bench] reuse R={R}: theta={th:.4f} max p99={max(errs):.3e} s/step={rec['s_per_step']:.4f}")
+        out.append(rec)
+    judge.close()
+    return out
+
+
 def force_source_digest():
     src = os.path.join(ROOT, "paper_1907_02289_amd", "csrc", "bh_force.hip")
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, n_group, theta, tree):
     """HBM bytes per force-kernel launch from the committed rocprofv3 counter
-    summary, or None when it is missing, for another workload, or taken on
-    a different force-kernel source."""
+    summary, or None when it is missing, or taken on another workload,
+    configuration or force-kernel source."""
     path = os.path.join(ROOT, "profiles", "force_kernel_traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256_16") != force_source_digest() or rec.get("workload") != workload:
+    if (rec.get("kernel_source_sha256_16") != force_source_digest() or rec.get("workload") != workload
+            or rec.get("n_group") != n_group or rec.get("theta") != theta or rec.get("tree", "cartesian") != tree):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -222,10 +302,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use theta = 0.5 for both paths")
     ap.add_argument("--n-group", type=int, default=256)
+    ap.add_argument("--tree", choices=("auto", "cartesian", "cylindrical"), default="auto",
+                    help="tree coordinates of the tuned path (auto: whichever is faster at matched error)")
     ap.add_argument("--theta-tuned", type=float, default=None, help="skip tuning, use this theta (tuned path)")
     ap.add_argument("--theta-plain", type=float, default=None, help="skip tuning, use this theta (plain path)")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
     ap.add_argument("--no-collisions", action="store_true", help="skip timing the collision branch")
+    ap.add_argument("--reuse-study", action="store_true",
+                    help="only the list-reuse study: matched-error theta and time per step for each rebuild interval")
     ap.add_argument("--learned", action="store_true",
                     help="also train, tune and time the learned-criterion form (off by default: see the design notes)")
     args = ap.parse_args()
@@ -258,6 +342,17 @@ def main():
     log(f"[bench] direct-sum judge on {sample.numel()} targets: {time.perf_counter() - t:.2f} s")
     judge.close()
 
+    if args.reuse_study:
+        r_cyl = np.hypot(sysm.x, sysm.y)
+        cyl = 0.5 * float(r_cyl.min() + r_cyl.max()) if args.tree == "cylindrical" else 0.0
+        recs = reuse_study(bh, w, dev0, sample, n, args.n_group, args.steps, cyl_radius=cyl)
+        best = min(recs, key=lambda r: r["s_per_step"])
+        print(json.dumps({"metric": "list-reuse study: s/step at matched p99 rel force err 1e-3 per rebuild interval",
+                          "config": {"workload": f"ring{n}", "n_group": args.n_group, "eps": w.eps, "dt": w.dt,
+                                     "tree_coordinates": "cylindrical" if cyl else "cartesian", "cyl_radius": cyl},
+                          "fastest_rebuild_every": best["rebuild_every"], "records": recs}), flush=True)
+        return
+
     # ---- matched error: theta per path (and per group size for the tuned path)
     paths = {
         "tuned": dict(precision=bh.FP32_REL, n_group=args.n_group, rebuild_every=R),
@@ -265,11 +360,18 @@ def main():
     }
     fixed = {"tuned": args.theta_tuned, "plain": args.theta_plain}
     group_sizes = [args.n_group] if (args.no_tune or args.theta_tuned is not None) else list(GROUP_SIZES)
+    # tree coordinates of the tuned path: Cartesian, or cylindrical around the
+    # ring's mid radius (Sec. 4.3)
+    r_cyl = np.hypot(sysm.x, sysm.y)
+    cyl_ref = 0.5 * float(r_cyl.min() + r_cyl.max())
+    coords = {"cartesian": 0.0, "cylindrical": cyl_ref}
+    tree_choices = [args.tree] if args.tree != "auto" else list(coords)
     autotune = []
     for name, p in paths.items():
         best = None
-        for ng in (group_sizes if name == "tuned" else [p["n_group"]]):
-            ctx = bh.Context(theta=0.5, eps=w.eps, precision=p["precision"], n_group=ng)
+        for ng, tc in ([(g, t) for t in tree_choices for g in group_sizes] if name == "tuned"
+                       else [(p["n_group"], "cartesian")]):
+            ctx = bh.Context(theta=0.5, eps=w.eps, precision=p["precision"], n_group=ng, cyl_radius=coords[tc])
             ctx.build_tree([dev0])
             if args.no_tune or fixed[name] is not None:
                 th = fixed[name] if fixed[name] is not None else 0.5
@@ -283,20 +385,24 @@ def main():
             ctx.forces(None)
             st = ctx.stage_times()
             cost = st["walk"] / p["rebuild_every"] + st["forces"]
-            log(f"[bench] {name} n_group={ng}: theta={th:.4f} p99={e[0]:.3e} cost {cost:.2f} ms")
+            log(f"[bench] {name} n_group={ng} {tc}: theta={th:.4f} p99={e[0]:.3e} cost {cost:.2f} ms")
             if name == "tuned":
-                autotune.append({"n_group": ng, "theta": th, "p99": e[0], "ms_walk_per_step_plus_force": cost})
+                autotune.append({"n_group": ng, "tree": tc, "theta": th, "p99": e[0],
+                                 "interactions_per_force_eval": ctx.query()["interactions"],
+                                 "ms_walk_per_step_plus_force": cost})
             if best is None or cost < best[0]:
-                best = (cost, ng, th, e)
+                best = (cost, ng, th, e, tc)
             ctx.close()
             torch.cuda.empty_cache()
-        p["n_group"], p["theta"], (p["p99"], p["p50"]) = best[1], best[2], best[3]
+        p["n_group"], p["theta"], (p["p99"], p["p50"]), p["tree"] = best[1], best[2], best[3], best[4]
+        p["cyl_radius"] = coords[best[4]]
 
     # ---- timed runs
     def timed(p, steps, warmup, leap_per_step):
         dev = {k: v.clone() for k, v in dev0.items()}
         ctx = bh.Context(theta=p["theta"], eps=w.eps, central_mass=w.central_mass, precision=p["precision"],
-                         n_group=p["n_group"], **p.get("learned", {}), **p.get("contact", {}))
+                         n_group=p["n_group"], cyl_radius=p.get("cyl_radius", 0.0), **p.get("learned", {}),
+                         **p.get("contact", {}))
         if "weights" in p:
             ctx.mlp_weights(set=p["weights"])
         ctx.step([dev], w.dt, 0, p["rebuild_every"])
@@ -362,6 +468,7 @@ def main():
             "workload": workload,
             "n_particles": n, "theta_tuned": paths["tuned"]["theta"], "theta_plain": paths["plain"]["theta"],
             "eps": w.eps, "dt": w.dt, "rebuild_every": R, "n_group": paths["tuned"]["n_group"],
+            "tree_coordinates": paths["tuned"]["tree"], "cyl_radius": paths["tuned"]["cyl_radius"],
             "step": f"one rebuild cycle = {R} KDK steps", "positions_and_integration": "f64",
         },
         "s_per_leapfrog_step": leap_t,
@@ -373,7 +480,9 @@ def main():
         "group_size_autotune": autotune,
         "force_kernel_ms": avg_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(workload),
+                     "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": measured_traffic(workload, paths["tuned"]["n_group"], paths["tuned"]["theta"],
+                                                 paths["tuned"]["tree"]),
                      "flops_per_interaction": FLOPS_PER_INTERACTION,
                      "frac_at_paper_31_flops": achieved * PAPER_FLOPS_PER_INTERACTION / FLOPS_PER_INTERACTION
                      / FP32_PEAK_TFLOPS},

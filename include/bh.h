@@ -103,6 +103,19 @@ typedef struct {
      * half-kicked ones after each drift (bh_step).  The contact terms are
      * evaluated in FP64 in both precisions.  kappa, eta >= 0, finite. */
     double r_coll, kappa, eta;
+    /* Tree coordinates (Sec. 4.3, Eq. (1)).  0: Cartesian.  > 0: for a
+     * narrow ring near this radius the keys, cells, groups and opening test
+     * use (phi, r, z): the root cell has side S = 2 pi cyl_radius, its phi
+     * axis spans one turn ([-pi, pi) onto 2^21 grid cells, periodic in the
+     * opening test), r and z start at their minimum.  Node moments, group
+     * centres and forces stay Cartesian.  The radial and vertical extents
+     * of every system must be below S (else BH_EINVAL from the build);
+     * not combined with BH_OPEN_LEARNED (BH_EINVAL).  The angle is computed
+     * with correctly rounded operations only (a series for arctan after
+     * reduction to |t| <= tan(pi/8)), so keys do not depend on a math
+     * library.  BH_EXPORT_ROOT_BOX then holds (-pi, min r, min z,
+     * 2^21 / S). */
+    double cyl_radius;
 } bh_params;
 
 /* bh_params.flags: replay list-reusing steps eagerly instead of from a HIP graph. */

@@ -298,7 +298,7 @@ def direct_accel(x, y, z, m, eps, G=1.0, vel=None, contact=None):
 
 
 def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
-        theta=None, n_leaf=8, n_grp=64, rebuild_every=1, contact=None, trace=None):
+        theta=None, n_leaf=8, n_grp=64, rebuild_every=1, contact=None, trace=None, cyl_r=0.0):
     """Kick-drift-kick leapfrog in FP64 (the integration step (4) of Sec. 4.2).
 
     theta=None uses the direct sum; otherwise Barnes-Hut with lists rebuilt
@@ -306,7 +306,8 @@ def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
     contact = (rc, kappa, eta) adds the collision branch of Eq. (2); its
     dashpot sees the velocities held when the force is evaluated: the
     initial ones for the first evaluation, the half-kicked ones after each
-    drift.  trace, if given, is called as trace(step, x, y, z, vx, vy, vz)
+    drift.  cyl_r > 0 builds the trees on cylindrical coordinates around
+    that radius.  trace, if given, is called as trace(step, x, y, z, vx, vy, vz)
     after every completed step.  Returns new copies of (x, y, z, vx, vy, vz).
     """
     x, y, z, vx, vy, vz = (np.array(a, dtype=np.float64, copy=True) for a in (x, y, z, vx, vy, vz))
@@ -320,7 +321,7 @@ def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
             ax, ay, az, _ = direct(x, y, z, m, eps, G, vel=vel, contact=contact)
         else:
             if state is None or step % rebuild_every == 0:
-                state = BHState(x, y, z, m, theta, n_leaf, n_grp)
+                state = BHState(x, y, z, m, theta, n_leaf, n_grp, cyl_r=cyl_r)
             else:
                 state.refresh(x, y, z, m)
             ax, ay, az, _, _ = state.accel(x, y, z, m, eps, G, vel, contact)

@@ -34,7 +34,7 @@ class Params(C.Structure):
                 ("n_leaf", C.c_int32), ("n_group", C.c_int32), ("precision", C.c_int32),
                 ("criterion", C.c_int32), ("theta_min", C.c_double), ("theta_max", C.c_double),
                 ("tau", C.c_double), ("flags", C.c_int32), ("r_coll", C.c_double), ("kappa", C.c_double),
-                ("eta", C.c_double)]
+                ("eta", C.c_double), ("cyl_radius", C.c_double)]
 
 
 class System(C.Structure):
@@ -126,10 +126,11 @@ class Context:
 
     def __init__(self, theta=0.5, eps=1e-3, G=1.0, central_mass=0.0, n_leaf=8, n_group=64,
                  precision=FP64, criterion=GEOMETRIC, theta_min=0.2, theta_max=1.0, tau=1e-3,
-                 use_graphs=True, r_coll=0.0, kappa=0.0, eta=0.0):
+                 use_graphs=True, r_coll=0.0, kappa=0.0, eta=0.0, cyl_radius=0.0):
         self.L = load_library()
         self.params = Params(theta, eps, G, central_mass, n_leaf, n_group, precision, criterion,
-                             theta_min, theta_max, tau, 0 if use_graphs else FLAG_NO_GRAPH, r_coll, kappa, eta)
+                             theta_min, theta_max, tau, 0 if use_graphs else FLAG_NO_GRAPH, r_coll, kappa, eta,
+                             cyl_radius)
         h = C.c_void_p()
         self._check(self.L.bh_create(C.byref(h), C.byref(self.params)), ctx=None)
         self.h = h

@@ -232,6 +232,7 @@ void refresh_state(bh_ctx *c) {
     d.rc = c->P.r_coll;
     d.kappa = c->P.kappa;
     d.eta = c->P.eta;
+    d.cyl_r = c->P.cyl_radius;
 }
 
 bh_status check_params(const bh_params *p) {
@@ -246,6 +247,8 @@ bh_status check_params(const bh_params *p) {
     if (!(p->r_coll >= 0.0) || !std::isfinite(p->r_coll)) return BH_EINVAL;
     if (!(p->kappa >= 0.0) || !std::isfinite(p->kappa)) return BH_EINVAL;
     if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return BH_EINVAL;
+    if (!(p->cyl_radius >= 0.0) || !std::isfinite(p->cyl_radius)) return BH_EINVAL;
+    if (p->cyl_radius > 0.0 && p->criterion == BH_OPEN_LEARNED) return BH_EINVAL;
     return BH_OK;
 }
 
@@ -420,6 +423,10 @@ bh_status rebuild(bh_ctx *c, hipStream_t s, bool from_caller) {
         if (c->h_cnt->flags[FLAG_NONFINITE]) {
             c->tree_valid = c->lists_valid = false;
             return fail(c, BH_EINVAL, "non-finite particle coordinate");
+        }
+        if (c->h_cnt->flags[FLAG_EXTENT]) {
+            c->tree_valid = c->lists_valid = false;
+            return fail(c, BH_EINVAL, "cylindrical tree: radial or vertical extent exceeds 2 pi cyl_radius");
         }
         if (c->h_cnt->flags[FLAG_NODE_OVF]) {
             STCHK(ensure_nodes(c, c->node_cap * 2));

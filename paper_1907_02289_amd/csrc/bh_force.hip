@@ -15,11 +15,12 @@
 // queue in order of decreasing interaction count, so the longest lists start
 // first and the tail is made of short ones.  All four waves of a workgroup
 // share one LDS tile of sources (the paper's cores sharing a cache on one
-// list).  A group of more than 64 particles gives each wave a 64-particle
-// chunk, the waves left over splitting the source range; a group of at most
-// 64 (32, 16) particles splits the source range over the four waves (and
-// over 2 or 4 sub-slices of 32 or 16 lanes inside each wave, the tile padded
-// with massless sources), so small groups do not leave most lanes idle.
+// list).  The waves take 64-particle chunks of the group, the waves left
+// over splitting the source range; a chunk of at most 32 (16) particles -- a
+// small group, or the last chunk of a larger one -- spreads its wave over 2
+// (4) sub-slices of 32 (16) lanes, each on its own part of the source range
+// (the tile padded with massless sources), so partial chunks do not leave
+// most of their lanes idle.
 // Partial sums are added in a fixed order, so results do not depend on
 // timing.
 //
@@ -32,10 +33,8 @@
 // over the same tile, for the candidates only: the contact decision
 // dx*dx + dy*dy + dz*dz <= rc^2 and the spring and dashpot terms are taken
 // in FP64 from the absolute positions and velocities, and summed in FP64
-// apart from the gravity sums.  The clamped loop (the 13-instruction body
-// plus a max and a min) runs only on tiles whose bounding box comes within
-// that bound of some particle of the wave; every other tile takes the plain
-// loop, which is then exact because no pair in it can reach the clamp.
+// apart from the gravity sums.  Particle tiles thus run the 13-instruction
+// body plus a max and a min; node tiles run the plain loop.
 #include "bh_internal.hpp"
 
 namespace {
@@ -181,10 +180,12 @@ __device__ __forceinline__ void contact_pass(const typename V4<R>::T *tile, cons
 
 // FP32: registers capped so that 6 workgroups (24 waves) fit a CU; the
 // pair loop needs the occupancy to hide LDS and rsqrt latency (measured:
-// 100 VGPRs / 4 waves per SIMD ran 18% slower).  FP64 keeps the default.
+// 100 VGPRs / 4 waves per SIMD ran 18% slower; the collision variant, at
+// 5 workgroups without spills, ran 3% slower than at 6 with a few).  FP64
+// keeps the default.
 template <typename R, bool COLL>
 struct ForceOcc {
-    static constexpr int blocks = sizeof(R) == 4 ? (COLL ? 5 : 6) : 1;
+    static constexpr int blocks = sizeof(R) == 4 ? 6 : 1;
 };
 
 template <typename R, bool POT, bool ZERO_EPS, bool COLL>
@@ -197,7 +198,6 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
     __shared__ uint32_t s_item;
     __shared__ uint32_t wsum[4];
     __shared__ uint32_t jidx[COLL ? TJ : 1];            // sorted index of each particle-tile entry
-    __shared__ R tbox[COLL ? 4 : 1][6];                  // per-wave bounds of a particle tile
     __shared__ double cacc[COLL ? 4 : 1][COLL ? FT : 1];  // per-thread FP64 contact sums
 
     const int tid = threadIdx.x;
@@ -225,18 +225,22 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
 
         for (uint32_t ib = 0; ib < gi.count; ib += FT) {
             const uint32_t nb = min((uint32_t)FT, gi.count - ib);
-            // lanes per particle chunk: a group of <= 16 (<= 32) particles splits
-            // each wave into 4 (2) sub-slices of the source range
-            const int cw = nb <= 16 ? 16 : (nb <= 32 ? 32 : 64);
-            const int sub = 64 / cw;
-            const int n_ic = cw < 64 ? 1 : (int)((nb + 63) >> 6);
+            // Waves take 64-particle chunks of the block (n_ic of them), the
+            // waves left over splitting the source range (split ways).  A chunk
+            // of at most 32 (16) particles -- a small group, or the last chunk
+            // of a larger one -- spreads its wave over 2 (4) sub-slices of its
+            // source range: cw lanes per particle, sub = 64 / cw parts.
+            const int n_ic = (int)((nb + 63) >> 6);
             const int split = 4 / n_ic;
             const int ichunk = w % n_ic;
             const int jslice = w / n_ic;
             const bool wave_on = jslice < split;
-            const int nslices = split * sub;
-            const int slice = jslice * sub + lane / cw;
-            const uint32_t il = cw < 64 ? (uint32_t)(lane % cw) : ichunk * 64 + lane;
+            const int cnt_w = min(64, (int)nb - 64 * ichunk);
+            const int cw = cnt_w <= 16 ? 16 : (cnt_w <= 32 ? 32 : 64);
+            const int sub = 64 / cw;
+            const int part = lane / cw;
+            const bool any_sub = (int)nb - 64 * (n_ic - 1) <= 32;   // the block's last chunk is sub-sliced
+            const uint32_t il = 64 * ichunk + lane % cw;
             const bool ion = wave_on && il < nb;
             const uint32_t i = gi.begin + ib + il;
             R xi = 0, yi = 0, zi = 0;
@@ -256,69 +260,55 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                 for (int a = 0; a < 4; ++a) cacc[a][tid] = 0.0;
             }
 
-            // The staged tile holds cntt sources: pad it with massless far
-            // sources to a whole number of sub-slices, then let every active
-            // wave (or sub-slice) run over its share.
-            // particles: whether the tile holds particle sources (the only
-            // ones the collision branch applies to)
+            // The staged tile holds cntt sources.  With a sub-sliced chunk in the
+            // block the tile is padded with massless far sources to a multiple of
+            // 4 split entries and cut at multiples of 4, so that every part has
+            // the same length; full chunks still stop at the last real entry.
+            // particles: whether the tile holds particle sources (the only ones
+            // the collision branch applies to).
             auto compute_tile = [&](uint32_t cntt, bool particles) {
-                const int L = ((int)cntt + nslices - 1) / nslices;
-                if (cw < 64)
-                    for (int t = (int)cntt + tid; t < L * nslices; t += FT)
-                        tile[t] = mk4<R>((R)1e18, (R)1e18, (R)1e18, (R)0);
+                const int ct = (int)cntt;
+                const int cntp = any_sub ? (ct + 4 * split - 1) / (4 * split) * (4 * split) : ct;
+                for (int t = ct + tid; t < cntp; t += FT) tile[t] = mk4<R>((R)1e18, (R)1e18, (R)1e18, (R)0);
                 __syncthreads();
                 if (wave_on) {
-                    bool plain = true;
-                    if constexpr (COLL) {
-                        // is any particle of the wave near the tile's bounding box?  The
-                        // gaps bound every pair's rounded distance from below (rounding
-                        // is monotone), so a wave with none near cannot meet the clamp.
-                        bool near = false;
-                        if (particles) {
-                            R b[6];
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                b[a] = fmin(fmin(tbox[0][a], tbox[1][a]), fmin(tbox[2][a], tbox[3][a]));
-                                b[a + 3] = fmax(fmax(tbox[0][a + 3], tbox[1][a + 3]),
-                                                fmax(tbox[2][a + 3], tbox[3][a + 3]));
-                            }
-                            const R gx = fmax((R)0, fmax(b[0] - xi, xi - b[3]));
-                            const R gy = fmax((R)0, fmax(b[1] - yi, yi - b[4]));
-                            const R gz = fmax((R)0, fmax(b[2] - zi, zi - b[5]));
-                            const R g2 = fma_r<R>(gx, gx, fma_r<R>(gy, gy, fma_r<R>(gz, gz, eps2)));
-                            near = __ballot(ion && g2 <= rcd2) != 0;
-                        }
-                        if (near) {
-                            plain = false;
-                            int jb, jl;
-                            if (cw == 64) {
-                                jb = (int)(cntt * jslice / split);
-                                jl = (int)(cntt * (jslice + 1) / split) - jb;
-                            } else {
-                                jb = slice * L;
-                                jl = L;
-                            }
-                            cmin = (R)1e30;
-                            if (cw == 64)
-                                interact<R, POT, ZERO_EPS, true>(tile, jb, jb + jl, xi, yi, zi, eps2, rce2, ax, ay,
-                                                                 az, pot, cmin);
-                            else
-                                interact_lanes<R, POT, ZERO_EPS, true>(tile, jb, jl, xi, yi, zi, eps2, rce2, ax,
-                                                                       ay, az, pot, cmin);
-                            if (__ballot(ion && cmin <= rcd2) != 0)
-                                contact_pass<R, POT>(tile, jidx, jb, jl, xi, yi, zi, eps2, rcd2, ion, i, d,
-                                                     &cacc[0][tid]);
-                        }
+                    int jb, je;
+                    if (any_sub) {
+                        const int q = cntp >> 2;
+                        jb = 4 * (q * jslice / split);
+                        je = 4 * (q * (jslice + 1) / split);
+                    } else {
+                        jb = ct * jslice / split;
+                        je = ct * (jslice + 1) / split;
                     }
-                    if (plain) {
-                        if (cw == 64) {
-                            const int j0 = (int)(cntt * jslice / split), j1 = (int)(cntt * (jslice + 1) / split);
-                            interact<R, POT, ZERO_EPS, false>(tile, j0, j1, xi, yi, zi, eps2, rce2, ax, ay, az, pot,
-                                                              cmin);
-                        } else {
-                            interact_lanes<R, POT, ZERO_EPS, false>(tile, slice * L, L, xi, yi, zi, eps2, rce2, ax,
-                                                                    ay, az, pot, cmin);
-                        }
+                    // this lane's part of the range: [jl0, jl0 + L)
+                    int jl0, L;
+                    if (sub == 1) {
+                        jl0 = jb;
+                        L = max(0, min(je, ct) - jb);
+                    } else {
+                        L = (je - jb) / sub;
+                        jl0 = jb + part * L;
+                    }
+                    bool clamp = false;
+                    if constexpr (COLL) clamp = particles;
+                    if (clamp) {
+                        cmin = (R)1e30;
+                        if (sub == 1)
+                            interact<R, POT, ZERO_EPS, true>(tile, jl0, jl0 + L, xi, yi, zi, eps2, rce2, ax, ay,
+                                                             az, pot, cmin);
+                        else
+                            interact_lanes<R, POT, ZERO_EPS, true>(tile, jl0, L, xi, yi, zi, eps2, rce2, ax, ay,
+                                                                   az, pot, cmin);
+                        if (__ballot(ion && cmin <= rcd2) != 0)
+                            contact_pass<R, POT>(tile, jidx, jl0, L, xi, yi, zi, eps2, rcd2, ion, i, d,
+                                                 &cacc[0][tid]);
+                    } else if (sub == 1) {
+                        interact<R, POT, ZERO_EPS, false>(tile, jl0, jl0 + L, xi, yi, zi, eps2, rce2, ax, ay, az,
+                                                          pot, cmin);
+                    } else {
+                        interact_lanes<R, POT, ZERO_EPS, false>(tile, jl0, L, xi, yi, zi, eps2, rce2, ax, ay, az,
+                                                                pot, cmin);
                     }
                 }
                 __syncthreads();
@@ -358,7 +348,6 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                 __syncthreads();
                 for (uint32_t p0 = 0; p0 < tot; p0 += TJ) {
                     const uint32_t cntt = min((uint32_t)TJ, tot - p0);
-                    T4 e = mk4<R>((R)0, (R)0, (R)0, (R)0);
                     if ((uint32_t)tid < cntt) {
                         const uint32_t f = p0 + tid;
                         uint32_t lo = 0, hi = nl - 1;          // last k with lscan[k] <= f
@@ -368,26 +357,8 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                         }
                         const uint32_t j = lbeg[lo] + (f - lscan[lo]);
                         const double4 q = d.pos[j];
-                        e = mk4<R>((R)(q.x - cen.x), (R)(q.y - cen.y), (R)(q.z - cen.z), (R)q.w);
-                        tile[tid] = e;
+                        tile[tid] = mk4<R>((R)(q.x - cen.x), (R)(q.y - cen.y), (R)(q.z - cen.z), (R)q.w);
                         if (COLL) jidx[tid] = j;
-                    }
-                    if constexpr (COLL) {
-                        // bounding box of the tile's entries, per wave
-                        const bool has = (uint32_t)tid < cntt;
-                        const R big = (R)1e30;
-                        const R lx = wave_min(has ? e.x : big), ly = wave_min(has ? e.y : big),
-                                lz = wave_min(has ? e.z : big);
-                        const R hx = wave_max(has ? e.x : -big), hy = wave_max(has ? e.y : -big),
-                                hz = wave_max(has ? e.z : -big);
-                        if (lane == 0) {
-                            tbox[w][0] = lx;
-                            tbox[w][1] = ly;
-                            tbox[w][2] = lz;
-                            tbox[w][3] = hx;
-                            tbox[w][4] = hy;
-                            tbox[w][5] = hz;
-                        }
                     }
                     compute_tile(cntt, true);
                 }

@@ -15,6 +15,7 @@ enum {
     FLAG_NODE_OVF = 1,          // node capacity exceeded
     FLAG_WALK_OVF = 2,          // a walk frontier/list scratch overflowed
     FLAG_POOL_OVF = 3,          // list pool capacity exceeded
+    FLAG_EXTENT = 4,            // cylindrical tree coordinates exceed the root cell
     FLAG_COUNT = 8
 };
 
@@ -182,6 +183,7 @@ struct DevState {
     double th2;                    // theta * theta
     double eps2, G, central_mass;
     double rc, kappa, eta;         // collision branch of Eq. (2); rc = 0: off
+    double cyl_r;                  // tree on cylindrical coordinates around this radius; 0: Cartesian
 };
 
 enum { WALK_GEOMETRIC = 0, WALK_LEARNED = 1, WALK_ENUMERATE = 2 };

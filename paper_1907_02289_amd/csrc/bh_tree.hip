@@ -12,6 +12,15 @@
 //     into its non-empty octants; nodes are numbered level by level.
 //   groups: the first node on the way down from the root with at most
 //     n_grp particles, or a leaf; ordered by first particle.
+//
+// Cylindrical tree coordinates (Sec. 4.3, Eq. (1)), when cyl_r > 0: for a
+// narrow ring near radius cyl_r, cyl_r phi, r and z are locally Cartesian,
+// so keys, cells and groups are built on (phi, r, z) while moments and
+// forces stay Cartesian.  The root cell has side S = 2 pi cyl_r; its phi
+// axis spans one turn, q = floor((phi + pi) 2^21 / (2 pi)); r and z use
+// q = floor((v - min v) 2^21 / S).  phi comes from angle_of below, made of
+// correctly rounded operations only, so the keys do not depend on a math
+// library.
 #include "bh_internal.hpp"
 
 namespace {
@@ -32,6 +41,53 @@ inline unsigned grid_for(size_t n, size_t cap_blocks = 8192) {
     if (b < 1) b = 1;
     if (b > cap_blocks) b = cap_blocks;
     return (unsigned)b;
+}
+
+// ---------------------------------------------------------------- cylindrical coordinates
+constexpr double CYL_PI = 3.141592653589793;
+constexpr double CYL_TAN_PI8 = 0.41421356237309503;   // tan(pi/8)
+
+// arctan t for |t| <= tan(pi/8): the Maclaurin series t - t^3/3 + t^5/5 - ...
+// (Abramowitz & Stegun 4.4.42) through t^29 (truncation below 2e-14),
+// Horner's rule in t^2 from the top term down, coefficients (-1)^k / (2k+1).
+__device__ __forceinline__ double atan_small(double t) {
+    const double t2 = t * t;
+    double p = 0.0;
+#pragma unroll
+    for (int k = 14; k >= 0; --k) {
+        double c = 1.0 / (double)(2 * k + 1);
+        if (k & 1) c = -c;
+        p = p * t2 + c;
+    }
+    return t * p;
+}
+
+// Angle of (x, y) in [-pi, pi]: t = min/max(|x|, |y|) in [0, 1], reduced
+// above tan(pi/8) by arctan t = pi/4 + arctan((t - 1)/(t + 1)) (A&S 4.4.34),
+// then reflected into the octant and quadrant of (x, y); (0, 0) gives 0.
+__device__ __forceinline__ double angle_of(double y, double x) {
+    const double ax = fabs(x), ay = fabs(y);
+    if (ax == 0.0 && ay == 0.0) return 0.0;
+    const bool swap = ay > ax;
+    const double t = swap ? ax / ay : ay / ax;
+    double a = (t > CYL_TAN_PI8) ? 0.25 * CYL_PI + atan_small((t - 1.0) / (t + 1.0)) : atan_small(t);
+    if (swap) a = 0.5 * CYL_PI - a;
+    if (x < 0.0) a = CYL_PI - a;
+    if (y < 0.0) a = -a;
+    return a;
+}
+
+// The coordinates the tree is built on.
+__device__ __forceinline__ void tree_coords(const DevState &d, double4 p, double c[3]) {
+    if (d.cyl_r > 0.0) {
+        c[0] = angle_of(p.y, p.x);
+        c[1] = sqrt(p.x * p.x + p.y * p.y);
+        c[2] = p.z;
+    } else {
+        c[0] = p.x;
+        c[1] = p.y;
+        c[2] = p.z;
+    }
 }
 
 // ---------------------------------------------------------------- load
@@ -55,11 +111,12 @@ __global__ void __launch_bounds__(TPB) k_box_partial(DevState d) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     bool bad = false;
     for (uint32_t i = b0 + blockIdx.x * TPB + threadIdx.x; i < b1; i += BOX_BLOCKS * TPB) {
-        double4 p = d.pos_in[i];
-        double c[3] = {p.x, p.y, p.z};
+        const double4 p = d.pos_in[i];
+        bad |= !isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z);
+        double c[3];
+        tree_coords(d, p, c);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            bad |= !isfinite(c[a]);
             lo[a] = fmin(lo[a], c[a]);
             hi[a] = fmax(hi[a], c[a]);
         }
@@ -102,6 +159,13 @@ __global__ void k_box_final(DevState d) {
             hi[a] = fmax(hi[a], p[3 + a]);
         }
     }
+    if (d.cyl_r > 0.0) {
+        // one turn of phi; r and z must fit the cell of side 2 pi cyl_r
+        const double S = (2.0 * CYL_PI) * d.cyl_r;
+        if (hi[1] - lo[1] >= S || hi[2] - lo[2] >= S) atomicOr(&d.cnt->flags[FLAG_EXTENT], 1u);
+        d.box[s] = make_double4(-CYL_PI, lo[1], lo[2], 2097152.0 / S);
+        return;
+    }
     double w = 0.0;
     for (int a = 0; a < 3; ++a) {
         double e = hi[a] - lo[a];
@@ -119,11 +183,14 @@ __global__ void k_keys(DevState d) {
         int s = sys_of(d.sys_off, d.n_sys, i);
         double4 b = d.box[s];
         double4 p = d.pos_in[i];
-        double c[3] = {p.x, p.y, p.z}, l[3] = {b.x, b.y, b.z};
+        double c[3], l[3] = {b.x, b.y, b.z};
+        tree_coords(d, p, c);
+        // the phi axis of cylindrical coordinates spans one turn
+        const double k0 = d.cyl_r > 0.0 ? 2097152.0 / (2.0 * CYL_PI) : b.w;
         uint32_t q[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            double t = (c[a] - l[a]) * b.w;
+            double t = (c[a] - l[a]) * (a == 0 ? k0 : b.w);
             double f = floor(t);
             q[a] = (f >= 2097151.0) ? 2097151u : (uint32_t)f;
         }

@@ -14,26 +14,42 @@
 // Opening test (the paper states none; reading): a node is accepted when it
 // lies outside the group's grid box and side < theta * distance from the
 // node's centre to the box, evaluated in doubled integer grid units with a
-// single FP64 multiply, so every device decides exactly alike.
+// single FP64 multiply, so every device decides exactly alike.  On
+// cylindrical tree coordinates (Sec. 4.3) the phi axis is periodic with one
+// turn = 2^21 grid units: its distance is that of the node's nearest image
+// (a node and a group box inside one turn overlap only directly).
 #include "bh_learned.hpp"
 
 namespace {
 
 constexpr int WALK_TPB = 256;
 
-__device__ __forceinline__ bool accept_cell(int4 glo, int4 ghi, int Lx, int Ly, int Lz, int level, double th2) {
+// doubled distance from the doubled coordinate C to [gl, gh]
+__device__ __forceinline__ int64_t gap2(int64_t C, int64_t gl, int64_t gh) {
+    int64_t da = 0;
+    da = (2 * gl - C > da) ? 2 * gl - C : da;
+    da = (C - 2 * gh > da) ? C - 2 * gh : da;
+    return da;
+}
+
+__device__ __forceinline__ bool accept_cell(int4 glo, int4 ghi, int Lx, int Ly, int Lz, int level, double th2,
+                                            bool periodic = false) {
     const int64_t s = (int64_t)1 << (BH_MAXLEVEL - level);
     const int64_t L[3] = {Lx, Ly, Lz};
     const int64_t gl[3] = {glo.x, glo.y, glo.z}, gh[3] = {ghi.x, ghi.y, ghi.z};
+    constexpr int64_t TURN2 = (int64_t)2 << BH_MAXLEVEL;    // one turn of phi, doubled units
     bool disjoint = false;
     int64_t d2 = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         disjoint |= (L[a] + s <= gl[a]) || (L[a] >= gh[a]);
         int64_t C = 2 * L[a] + s;
-        int64_t da = 0;
-        da = (2 * gl[a] - C > da) ? 2 * gl[a] - C : da;
-        da = (C - 2 * gh[a] > da) ? C - 2 * gh[a] : da;
+        int64_t da = gap2(C, gl[a], gh[a]);
+        if (a == 0 && periodic) {
+            const int64_t dm = gap2(C - TURN2, gl[a], gh[a]), dp = gap2(C + TURN2, gl[a], gh[a]);
+            da = dm < da ? dm : da;
+            da = dp < da ? dp : da;
+        }
         d2 += da * da;
     }
     const int64_t s2 = (2 * s) * (2 * s);
@@ -56,7 +72,7 @@ __device__ __forceinline__ bool decide(const DevState &d, const GroupCtx &gc, ui
     const int level = (int)((uint32_t)wr.x >> 24);
     const int Lx = wr.x & 0xffffff, Ly = wr.y & 0xffffff, Lz = wr.z;
     *cand = false;
-    if (d.walk_mode == WALK_GEOMETRIC) return accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2);
+    if (d.walk_mode == WALK_GEOMETRIC) return accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2, d.cyl_r > 0.0);
     if (accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2_min)) return true;
     if (!accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2_max)) return false;
     const uint32_t cnt = d.nd_count[v];
