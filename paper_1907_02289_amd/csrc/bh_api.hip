@@ -51,7 +51,7 @@ struct bh_ctx {
     uint32_t walk_waves = 0, walk_front = 4096, walk_list = 8192;
 
     // device buffers
-    DevBuf sys_off_b, sys_tab_b, acc_tab_b, box_b, box_part_b;
+    DevBuf sys_off_b, sys_tab_b, acc_tab_b, box_b, box_part_b, sys_m0_b;
     DevBuf pos_in, vel_in, idx_in, pos, vel, acc, idx;
     DevBuf key, key_tmp, val, val_tmp, hist, scan_tmp;
     DevBuf nd_prefix, nd_begin, nd_count, nd_first, nd_meta, nd_walk, nd_mom, nd_quad, tmp_a, tmp_b;
@@ -164,6 +164,7 @@ void refresh_state(bh_ctx *c) {
     d.sys_tab = P<SysPtr>(c->sys_tab_b);
     d.box = P<double4>(c->box_b);
     d.box_part = P<double>(c->box_part_b);
+    d.sys_m0 = P<double>(c->sys_m0_b);
     d.pos_in = P<double4>(c->pos_in);
     d.vel_in = P<double4>(c->vel_in);
     d.idx_in = P<uint32_t>(c->idx_in);
@@ -282,7 +283,8 @@ bh_status ensure_systems(bh_ctx *c, int n_sys) {
     HIPCHK(c, grow(c->sys_tab_b, cap * sizeof(SysPtr)));
     HIPCHK(c, grow(c->acc_tab_b, cap * sizeof(bhk::AccPtr)));
     HIPCHK(c, grow(c->box_b, cap * sizeof(double4)));
-    HIPCHK(c, grow(c->box_part_b, (size_t)cap * BOX_BLOCKS * 6 * sizeof(double)));
+    HIPCHK(c, grow(c->box_part_b, (size_t)cap * BOX_BLOCKS * 8 * sizeof(double)));
+    HIPCHK(c, grow(c->sys_m0_b, cap * sizeof(double)));
     if (c->h_systab) (void)hipHostFree(c->h_systab);
     if (c->h_acctab) (void)hipHostFree(c->h_acctab);
     c->h_systab = nullptr;
@@ -628,7 +630,7 @@ bh_status bh_create(bh_ctx **out, const bh_params *p) {
 bh_status bh_destroy(bh_ctx *c) {
     if (!c) return BH_EINVAL;
     (void)hipDeviceSynchronize();
-    DevBuf *all[] = {&c->sys_off_b, &c->sys_tab_b, &c->acc_tab_b, &c->box_b, &c->box_part_b, &c->pos_in,
+    DevBuf *all[] = {&c->sys_off_b, &c->sys_tab_b, &c->acc_tab_b, &c->box_b, &c->box_part_b, &c->sys_m0_b, &c->pos_in,
                      &c->vel_in, &c->idx_in, &c->pos, &c->vel, &c->acc, &c->idx, &c->key, &c->key_tmp,
                      &c->val, &c->val_tmp, &c->hist, &c->scan_tmp, &c->nd_prefix, &c->nd_begin, &c->nd_count,
                      &c->nd_first, &c->nd_meta, &c->nd_walk, &c->nd_mom, &c->nd_quad, &c->tmp_a, &c->tmp_b,

@@ -75,7 +75,9 @@ __device__ __forceinline__ double fma_r<double>(double a, double b, double c) { 
 // the pair arithmetic (every lane reads the same LDS entry: a broadcast).
 // CLAMP (particle sources with the collision branch on): r^2 + eps^2 is
 // raised to at least rce2 = rc^2 + eps^2 and its smallest value kept in cmin.
-template <typename R, bool POT, bool ZERO_EPS, bool CLAMP>
+// EQM (particle sources of an equal-mass system): the common mass is taken
+// out of the loop and applied to the sums at the end.
+template <typename R, bool POT, bool ZERO_EPS, bool CLAMP, bool EQM>
 __device__ __forceinline__ void interact(const typename V4<R>::T *tile, int j0, int j1, R xi, R yi, R zi, R eps2,
                                          R rce2, R &ax, R &ay, R &az, R &pot, R &cmin) {
     j0 = __builtin_amdgcn_readfirstlane(j0);
@@ -91,7 +93,7 @@ __device__ __forceinline__ void interact(const typename V4<R>::T *tile, int j0, 
         }
         R ri = rsqrt_r<R>(r2);
         if (ZERO_EPS && !CLAMP) ri = (r2 > (R)0) ? ri : (R)0;
-        const R mri = s.w * ri;
+        const R mri = EQM ? ri : s.w * ri;
         const R f = mri * (ri * ri);
         ax = fma_r<R>(f, dx, ax);
         ay = fma_r<R>(f, dy, ay);
@@ -102,7 +104,7 @@ __device__ __forceinline__ void interact(const typename V4<R>::T *tile, int j0, 
 
 // The same pass when the lanes of a wave work on different source ranges
 // (sub-slices of a small group): lane base jb, common length L.
-template <typename R, bool POT, bool ZERO_EPS, bool CLAMP>
+template <typename R, bool POT, bool ZERO_EPS, bool CLAMP, bool EQM>
 __device__ __forceinline__ void interact_lanes(const typename V4<R>::T *tile, int jb, int L, R xi, R yi, R zi,
                                                R eps2, R rce2, R &ax, R &ay, R &az, R &pot, R &cmin) {
     L = __builtin_amdgcn_readfirstlane(L);
@@ -118,13 +120,24 @@ __device__ __forceinline__ void interact_lanes(const typename V4<R>::T *tile, in
         }
         R ri = rsqrt_r<R>(r2);
         if (ZERO_EPS && !CLAMP) ri = (r2 > (R)0) ? ri : (R)0;
-        const R mri = s.w * ri;
+        const R mri = EQM ? ri : s.w * ri;
         const R f = mri * (ri * ri);
         ax = fma_r<R>(f, dx, ax);
         ay = fma_r<R>(f, dy, ay);
         az = fma_r<R>(f, dz, az);
         if (POT) pot -= mri;
     }
+}
+
+// One lane's pass over tile entries [jl0, jl0 + L): the whole wave on one
+// range (sub == 1) or each sub-slice on its own.
+template <typename R, bool POT, bool ZERO_EPS, bool CLAMP, bool EQM>
+__device__ __forceinline__ void tile_pass(const typename V4<R>::T *tile, int sub, int jl0, int L, R xi, R yi, R zi,
+                                          R eps2, R rce2, R &ax, R &ay, R &az, R &pot, R &cmin) {
+    if (sub == 1)
+        interact<R, POT, ZERO_EPS, CLAMP, EQM>(tile, jl0, jl0 + L, xi, yi, zi, eps2, rce2, ax, ay, az, pot, cmin);
+    else
+        interact_lanes<R, POT, ZERO_EPS, CLAMP, EQM>(tile, jl0, L, xi, yi, zi, eps2, rce2, ax, ay, az, pot, cmin);
 }
 
 // Contact terms of Eq. (2) for the pair (i, j), both sorted indices, in
@@ -220,6 +233,11 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
         const uint32_t g = __builtin_amdgcn_readfirstlane(d.order[item]);
         const GroupInfo gi = d.grp[g];
         const double4 cen = d.g_cen[g];
+        // FP32: an equal-mass system's particles enter the pair loop with unit
+        // mass, node masses in units of that mass, the sums scaled at the end
+        const double m0 = sizeof(R) == 4 ? d.sys_m0[gi.sys] : 0.0;
+        const bool eqm = m0 > 0.0;
+        const double gscale = eqm ? d.G * m0 : d.G;
         const unsigned long long pc0 = d.g_pc_off[g], pp0 = d.g_pp_off[g];
         const uint32_t npc = d.g_pc_len[g], npp = d.g_pp_len[g];
 
@@ -292,23 +310,24 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                     }
                     bool clamp = false;
                     if constexpr (COLL) clamp = particles;
+                    const bool eq = particles && eqm;
                     if (clamp) {
                         cmin = (R)1e30;
-                        if (sub == 1)
-                            interact<R, POT, ZERO_EPS, true>(tile, jl0, jl0 + L, xi, yi, zi, eps2, rce2, ax, ay,
-                                                             az, pot, cmin);
+                        if (eq)
+                            tile_pass<R, POT, ZERO_EPS, true, true>(tile, sub, jl0, L, xi, yi, zi, eps2, rce2, ax, ay,
+                                                                    az, pot, cmin);
                         else
-                            interact_lanes<R, POT, ZERO_EPS, true>(tile, jl0, L, xi, yi, zi, eps2, rce2, ax, ay,
-                                                                   az, pot, cmin);
+                            tile_pass<R, POT, ZERO_EPS, true, false>(tile, sub, jl0, L, xi, yi, zi, eps2, rce2, ax,
+                                                                     ay, az, pot, cmin);
                         if (__ballot(ion && cmin <= rcd2) != 0)
                             contact_pass<R, POT>(tile, jidx, jl0, L, xi, yi, zi, eps2, rcd2, ion, i, d,
                                                  &cacc[0][tid]);
-                    } else if (sub == 1) {
-                        interact<R, POT, ZERO_EPS, false>(tile, jl0, jl0 + L, xi, yi, zi, eps2, rce2, ax, ay, az,
-                                                          pot, cmin);
+                    } else if (eq) {
+                        tile_pass<R, POT, ZERO_EPS, false, true>(tile, sub, jl0, L, xi, yi, zi, eps2, rce2, ax, ay,
+                                                                 az, pot, cmin);
                     } else {
-                        interact_lanes<R, POT, ZERO_EPS, false>(tile, jl0, L, xi, yi, zi, eps2, rce2, ax, ay, az,
-                                                                pot, cmin);
+                        tile_pass<R, POT, ZERO_EPS, false, false>(tile, sub, jl0, L, xi, yi, zi, eps2, rce2, ax, ay,
+                                                                  az, pot, cmin);
                     }
                 }
                 __syncthreads();
@@ -319,7 +338,7 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                 const uint32_t cntt = min((uint32_t)TJ, npc - t0);
                 if ((uint32_t)tid < cntt) {
                     const double4 m = d.nd_mom[d.pc_pool[pc0 + t0 + tid]];
-                    tile[tid] = mk4<R>((R)(m.x - cen.x), (R)(m.y - cen.y), (R)(m.z - cen.z), (R)m.w);
+                    tile[tid] = mk4<R>((R)(m.x - cen.x), (R)(m.y - cen.y), (R)(m.z - cen.z), (R)(eqm ? m.w / m0 : m.w));
                 }
                 compute_tile(cntt, false);
             }
@@ -389,7 +408,7 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                     sz += red[2][ww][lane];
                     sp += red[3][ww][lane];
                 }
-                double gx = d.G * (double)sx, gy = d.G * (double)sy, gz = d.G * (double)sz;
+                double gx = gscale * (double)sx, gy = gscale * (double)sy, gz = gscale * (double)sz;
                 if (d.amag) d.amag[i] = sqrt(gx * gx + gy * gy + gz * gz);
                 if (d.central_mass != 0.0) {
                     const double4 p = d.pos[i];
@@ -400,7 +419,7 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                     gy += f * p.y;
                     gz += f * p.z;
                 }
-                double gp = POT ? d.G * (double)sp : 0.0;
+                double gp = POT ? gscale * (double)sp : 0.0;
                 if (COLL) {
                     // contact sums of the threads that worked on particle i, in a fixed order
                     double cx = 0, cy = 0, cz = 0, cp = 0;

@@ -135,7 +135,8 @@ struct DevState {
     const uint32_t *sys_off;       // [n_sys+1]
     const SysPtr *sys_tab;         // [n_sys]
     double4 *box;                  // [n_sys]: lo x, y, z, 2^21 / S
-    double *box_part;              // [n_sys][BOX_BLOCKS][6]
+    double *box_part;              // [n_sys][BOX_BLOCKS][8]: min, max of the tree coordinates and of the mass
+    double *sys_m0;                // [n_sys] the common particle mass of a system, 0 when masses differ
     // particles: input order of the current build and sorted order
     double4 *pos_in, *vel_in;
     uint32_t *idx_in;

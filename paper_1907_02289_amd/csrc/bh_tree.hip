@@ -108,57 +108,61 @@ __global__ void k_load(DevState d) {
 __global__ void __launch_bounds__(TPB) k_box_partial(DevState d) {
     const int s = blockIdx.y;
     const uint32_t b0 = d.sys_off[s], b1 = d.sys_off[s + 1];
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    // per axis 0..2 the tree coordinates, axis 3 the mass
+    double lo[4] = {INFINITY, INFINITY, INFINITY, INFINITY}, hi[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
     bool bad = false;
     for (uint32_t i = b0 + blockIdx.x * TPB + threadIdx.x; i < b1; i += BOX_BLOCKS * TPB) {
         const double4 p = d.pos_in[i];
         bad |= !isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z);
-        double c[3];
+        double c[4];
         tree_coords(d, p, c);
+        c[3] = p.w;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
+        for (int a = 0; a < 4; ++a) {
             lo[a] = fmin(lo[a], c[a]);
             hi[a] = fmax(hi[a], c[a]);
         }
     }
     if (bad) atomicOr(&d.cnt->flags[FLAG_NONFINITE], 1u);
-    __shared__ double red[TPB / 64][6];
+    __shared__ double red[TPB / 64][8];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 4; ++a) {
         lo[a] = wave_min(lo[a]);
         hi[a] = wave_max(hi[a]);
     }
     const int w = threadIdx.x >> 6;
     if (__lane_id() == 0) {
-        for (int a = 0; a < 3; ++a) {
+        for (int a = 0; a < 4; ++a) {
             red[w][a] = lo[a];
-            red[w][3 + a] = hi[a];
+            red[w][4 + a] = hi[a];
         }
     }
     __syncthreads();
-    if (threadIdx.x < 6) {
+    if (threadIdx.x < 8) {
         int a = threadIdx.x;
         double v = red[0][a];
-        for (int k = 1; k < TPB / 64; ++k) v = (a < 3) ? fmin(v, red[k][a]) : fmax(v, red[k][a]);
-        d.box_part[((size_t)s * BOX_BLOCKS + blockIdx.x) * 6 + a] = v;
+        for (int k = 1; k < TPB / 64; ++k) v = (a < 4) ? fmin(v, red[k][a]) : fmax(v, red[k][a]);
+        d.box_part[((size_t)s * BOX_BLOCKS + blockIdx.x) * 8 + a] = v;
     }
 }
 
 __global__ void k_box_final(DevState d) {
     const int s = blockIdx.x;
     if (threadIdx.x != 0) return;
-    double lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
+    double lo[4], hi[4];
+    for (int a = 0; a < 4; ++a) {
         lo[a] = INFINITY;
         hi[a] = -INFINITY;
     }
     for (int b = 0; b < BOX_BLOCKS; ++b) {
-        const double *p = d.box_part + ((size_t)s * BOX_BLOCKS + b) * 6;
-        for (int a = 0; a < 3; ++a) {
+        const double *p = d.box_part + ((size_t)s * BOX_BLOCKS + b) * 8;
+        for (int a = 0; a < 4; ++a) {
             lo[a] = fmin(lo[a], p[a]);
-            hi[a] = fmax(hi[a], p[3 + a]);
+            hi[a] = fmax(hi[a], p[4 + a]);
         }
     }
+    // equal-mass systems let the force kernel take the common mass out of the pair loop
+    d.sys_m0[s] = (lo[3] == hi[3] && lo[3] > 0.0) ? lo[3] : 0.0;
     if (d.cyl_r > 0.0) {
         // one turn of phi; r and z must fit the cell of side 2 pi cyl_r
         const double S = (2.0 * CYL_PI) * d.cyl_r;

@@ -110,6 +110,17 @@ def _coincident():
 CASES.append(("coincident40", _coincident, 0.5, 1e-3, 8, 32))
 
 
+def _mixed_masses():
+    """Unequal masses: the FP32 kernel keeps the per-source mass in its loop
+    (equal-mass systems take it out)."""
+    s = inputs.ring(6000, 6)
+    s.m[:] = np.random.default_rng(6).uniform(0.5, 1.5, s.n) / s.n
+    return s
+
+
+CASES.append(("ring6000_mixed_masses", _mixed_masses, 0.5, 1e-3, 8, 100))
+
+
 @pytest.mark.parametrize("name,make,theta,eps,n_leaf,n_grp", CASES, ids=[c[0] for c in CASES])
 def test_structures_and_fp64_forces(torch_cuda, name, make, theta, eps, n_leaf, n_grp):
     torch = torch_cuda
@@ -129,8 +140,8 @@ def test_structures_and_fp64_forces(torch_cuda, name, make, theta, eps, n_leaf, 
     ctx.close()
 
 
-@pytest.mark.parametrize("name,make,theta,eps,n_leaf,n_grp", CASES[:3] + CASES[-2:],
-                         ids=[c[0] for c in CASES[:3] + CASES[-2:]])
+@pytest.mark.parametrize("name,make,theta,eps,n_leaf,n_grp", CASES[:3] + CASES[-3:],
+                         ids=[c[0] for c in CASES[:3] + CASES[-3:]])
 def test_fp32_relative_forces(torch_cuda, name, make, theta, eps, n_leaf, n_grp):
     torch = torch_cuda
     _log(f"[gpu] fp32 {name}")
