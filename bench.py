@@ -257,14 +257,18 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "repeats": 3}))
 
 
-def cpu_baseline(system, theta, n_grp, eps, rebuild_every, n_sample_groups=1024, seed=0):
-    """The oracle on the host cores: full tree build of the same ring, then
-    walk + forces for a random sample of groups; interactions of the sample
-    over the time of the sample's work (build prorated to the sample's share
-    of groups and to one force evaluation of its reuse cycle)."""
+def cpu_baseline(system, theta, n_grp, eps, rebuild_every, cyl_radius=0.0, n_sample_groups=1024, seed=0):
+    """The oracle on the host cores: full tree build of the same ring (in the
+    tuned path's tree coordinates), then walk + forces for a random sample of
+    groups; interactions of the sample over the time of the sample's work
+    (build prorated to the sample's share of groups and to one force
+    evaluation of its reuse cycle)."""
     import oracle
     t0 = time.perf_counter()
-    _, _, _, key = oracle.keys(system.x, system.y, system.z)
+    if cyl_radius > 0.0:
+        _, _, _, key = oracle.keys_cyl(system.x, system.y, system.z, cyl_radius)
+    else:
+        _, _, _, key = oracle.keys(system.x, system.y, system.z)
     perm = oracle.sort_perm(key)
     skey = key[perm]
     t = oracle.tree(skey, 8)
@@ -276,7 +280,7 @@ def cpu_baseline(system, theta, n_grp, eps, rebuild_every, n_sample_groups=1024,
     rng = np.random.default_rng(seed)
     sel = np.sort(rng.choice(g.size, min(n_sample_groups, g.size), replace=False))
     t1 = time.perf_counter()
-    pc_off, pc, pp_off, pp = oracle.lists(gbox[sel], t, theta)
+    pc_off, pc, pp_off, pp = oracle.lists(gbox[sel], t, theta, oracle.CYL_PERIOD if cyl_radius > 0.0 else 0)
     oracle.forces(g[sel], t, xs, ys, zs, ms, mom, pc_off, pc, pp_off, pp, eps)
     t_sample = time.perf_counter() - t1
     cnt = t["count"].astype(np.int64)
@@ -285,7 +289,8 @@ def cpu_baseline(system, theta, n_grp, eps, rebuild_every, n_sample_groups=1024,
     share = sel.size / g.size
     t_total = t_sample + t_build * share / rebuild_every
     return dict(value=inter / t_total, unit="interactions/s", cores=oracle.n_threads(), kind="oracle",
-                sample=(f"16M ring, theta={theta:.4f}, n_grp={n_grp}: oracle tree build of all {system.n} "
+                sample=(f"16M ring, theta={theta:.4f}, n_grp={n_grp}, "
+                        f"{'cylindrical' if cyl_radius > 0.0 else 'Cartesian'} tree: oracle tree build of all {system.n} "
                         f"particles ({t_build:.1f} s, prorated {share:.4f} of groups / {rebuild_every} steps) "
                         f"+ walk and FP64 forces of {sel.size} random groups ({t_sample:.2f} s, "
                         f"{inter} interactions)"),
@@ -507,7 +512,8 @@ def main():
                           "interactions_vs_geometric": (lr["interactions"] / max(1, lr["force_evals"])) / per_launch}
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(sysm, paths["tuned"]["theta"], paths["tuned"]["n_group"], w.eps, R)
+        out["cpu_baseline"] = cpu_baseline(sysm, paths["tuned"]["theta"], paths["tuned"]["n_group"], w.eps, R,
+                                           paths["tuned"]["cyl_radius"])
     print(json.dumps(out), flush=True)
 
 
