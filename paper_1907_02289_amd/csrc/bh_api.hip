@@ -473,10 +473,13 @@ bh_status walk_until_fits(bh_ctx *c, hipStream_t s) {
             continue;
         }
         if (h.flags[FLAG_POOL_OVF]) {
+            // the pools are grown to what this walk needed, so one more pass fits
+            if (attempt > 40) return fail(c, BH_ECAPACITY, "list pools cannot grow further");
             STCHK(ensure_pools(c, h.pc_used + h.pc_used / 4 + 1024, h.pp_used + h.pp_used / 4 + 1024));
             continue;
         }
         if (c->walk_mode == WALK_ENUMERATE && h.cand_used > c->cand_cap) {
+            if (attempt > 40) return fail(c, BH_ECAPACITY, "candidate buffer cannot grow further");
             uint64_t cap = h.cand_used + h.cand_used / 4 + 1024;
             HIPCHK(c, grow(c->cand, cap * sizeof(uint2)));
             c->cand_cap = cap;
