@@ -119,6 +119,7 @@ def _mixed_masses():
 
 
 CASES.append(("ring6000_mixed_masses", _mixed_masses, 0.5, 1e-3, 8, 100))
+CASES.append(("ring5000_eps0", lambda: inputs.ring(5000, 8), 0.5, 0.0, 8, 64))
 
 
 @pytest.mark.parametrize("name,make,theta,eps,n_leaf,n_grp", CASES, ids=[c[0] for c in CASES])
@@ -140,8 +141,8 @@ def test_structures_and_fp64_forces(torch_cuda, name, make, theta, eps, n_leaf, 
     ctx.close()
 
 
-@pytest.mark.parametrize("name,make,theta,eps,n_leaf,n_grp", CASES[:3] + CASES[-3:],
-                         ids=[c[0] for c in CASES[:3] + CASES[-3:]])
+@pytest.mark.parametrize("name,make,theta,eps,n_leaf,n_grp", CASES[:3] + CASES[-4:],
+                         ids=[c[0] for c in CASES[:3] + CASES[-4:]])
 def test_fp32_relative_forces(torch_cuda, name, make, theta, eps, n_leaf, n_grp):
     torch = torch_cuda
     _log(f"[gpu] fp32 {name}")
@@ -188,6 +189,30 @@ def test_batched_systems_match_single(torch_cuda):
         g = {q: v.cpu().numpy() for q, v in outs[k].items()}
         err = np.sqrt((g["ax"] - ax) ** 2 + (g["ay"] - ay) ** 2 + (g["az"] - az) ** 2)
         assert np.all(err <= 1e-12 * mag)
+    ctx.close()
+
+
+def test_batched_fp32_equal_and_unequal_masses(torch_cuda):
+    """FP32 in one launch over systems with equal masses (the common mass is
+    taken out of the pair loop) and with unequal masses: each system within
+    the FP32 bar of the oracle on that system alone."""
+    torch = torch_cuda
+    _log("[gpu] batched fp32, equal and unequal masses")
+    a = inputs.ring(7000, 21)
+    b = inputs.ring(5000, 22)
+    b.m[:] = np.random.default_rng(22).uniform(0.2, 1.8, b.n) / b.n
+    systems = [a, b, inputs.plummer(3000, 23)]
+    ctx, dev = _gpu_build(torch, systems, 0.5, 1e-3, 8, 128, precision=1)
+    outs = [{k: torch.zeros(s.n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")} for s in systems]
+    ctx.forces(outs)
+    torch.cuda.synchronize()
+    for k, s in enumerate(systems):
+        st = oracle.BHState(s.x, s.y, s.z, s.m, 0.5, 8, 128)
+        ax, ay, az, _, _ = st.accel(s.x, s.y, s.z, s.m, 1e-3)
+        g = {q: v.cpu().numpy() for q, v in outs[k].items()}
+        rel = np.sqrt((g["ax"] - ax) ** 2 + (g["ay"] - ay) ** 2 + (g["az"] - az) ** 2) / np.sqrt(ax ** 2 + ay ** 2 + az ** 2)
+        _log(f"    system {k}: median {np.median(rel):.2e} max {rel.max():.2e}")
+        assert np.median(rel) <= 1e-5
     ctx.close()
 
 
