@@ -68,11 +68,16 @@ struct GroupCtx {
 // (single-particle nodes accepted, nodes above the count cap: the theta test).
 // ENUMERATE: the theta_min test; *cand reports whether (group, v) lies in the
 // band and is a training candidate.
+// GEO: the kernel instance that serves only the geometric rule, without the
+// registers of the network inference (the other instance takes the rule from
+// d.walk_mode).
+template <bool GEO>
 __device__ __forceinline__ bool decide(const DevState &d, const GroupCtx &gc, uint32_t v, int4 wr, bool *cand) {
     const int level = (int)((uint32_t)wr.x >> 24);
     const int Lx = wr.x & 0xffffff, Ly = wr.y & 0xffffff, Lz = wr.z;
     *cand = false;
-    if (d.walk_mode == WALK_GEOMETRIC) return accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2, d.cyl_r > 0.0);
+    if (GEO || d.walk_mode == WALK_GEOMETRIC)
+        return accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2, d.cyl_r > 0.0);
     if (accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2_min)) return true;
     if (!accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2_max)) return false;
     const uint32_t cnt = d.nd_count[v];
@@ -88,6 +93,7 @@ __device__ __forceinline__ bool decide(const DevState &d, const GroupCtx &gc, ui
     return learned_accept(d.mlp, pg, mom.w, gc.amin, d.tau, d.G);
 }
 
+template <bool GEO>
 __global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
     const uint32_t wave = (blockIdx.x * WALK_TPB + threadIdx.x) >> 6;
     if (wave >= d.walk_waves) return;
@@ -109,7 +115,7 @@ __global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
         GroupCtx gc;
         gc.glo = d.g_lo[g];
         gc.ghi = d.g_hi[g];
-        if (d.walk_mode != WALK_GEOMETRIC) {
+        if (!GEO && d.walk_mode != WALK_GEOMETRIC) {
             gc.cen = d.g_cen[g];
             gc.rad = d.g_rad[g];
             gc.amin = d.walk_mode == WALK_LEARNED ? d.g_amin[g] : 0.0;
@@ -117,7 +123,7 @@ __global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
             gc.S = (double)(1u << BH_MAXLEVEL) / d.box[gi.sys].w;
         }
         // the enumerating walk visits only the sampled groups and stores no lists
-        const bool enumerate = d.walk_mode == WALK_ENUMERATE;
+        const bool enumerate = !GEO && d.walk_mode == WALK_ENUMERATE;
         const bool record = enumerate && (g % d.group_stride) == 0;
         if (enumerate && !record) {
             if (lane == 0) {
@@ -142,7 +148,7 @@ __global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
                 int4 wr = valid ? d.nd_walk[v] : make_int4(0, 0, 0, 0);
                 const int nch = (int)((uint32_t)wr.y >> 24);
                 bool is_cand = false;
-                const bool acc = valid && decide(d, gc, v, wr, &is_cand);
+                const bool acc = valid && decide<GEO>(d, gc, v, wr, &is_cand);
                 is_cand = is_cand && valid && record;
                 const uint64_t mc = __ballot(is_cand);
                 if (mc) {
@@ -257,7 +263,10 @@ namespace bhk {
 void walk(const DevState &d, hipStream_t s) {
     k_walk_reset<<<1, 64, 0, s>>>(d);
     unsigned blocks = (d.walk_waves * 64 + WALK_TPB - 1) / WALK_TPB;
-    k_walk<<<blocks, WALK_TPB, 0, s>>>(d);
+    if (d.walk_mode == WALK_GEOMETRIC)
+        k_walk<true><<<blocks, WALK_TPB, 0, s>>>(d);
+    else
+        k_walk<false><<<blocks, WALK_TPB, 0, s>>>(d);
 }
 
 void order_groups(const DevState &d, uint32_t n_groups, uint64_t *key_a, uint32_t *val_a, uint64_t *key_b,
