@@ -231,17 +231,19 @@ def force_source_digest():
 
 def measured_traffic(workload, n_group, theta, tree):
     """HBM bytes per force-kernel launch from the committed rocprofv3 counter
-    summary, or None when it is missing, or taken on another workload,
-    configuration or force-kernel source."""
+    summaries (one record per configuration), or None when none was taken on
+    this workload, configuration and force-kernel source."""
     path = os.path.join(ROOT, "profiles", "force_kernel_traffic.json")
     try:
-        rec = json.load(open(path))
+        recs = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if (rec.get("kernel_source_sha256_16") != force_source_digest() or rec.get("workload") != workload
-            or rec.get("n_group") != n_group or rec.get("theta") != theta or rec.get("tree", "cartesian") != tree):
-        return None
-    return rec.get("hbm_bytes_per_launch")
+    for rec in (recs if isinstance(recs, list) else [recs]):
+        if (rec.get("kernel_source_sha256_16") == force_source_digest() and rec.get("workload") == workload
+                and rec.get("n_group") == n_group and rec.get("theta") == theta
+                and rec.get("tree", "cartesian") == tree):
+            return rec.get("hbm_bytes_per_launch")
+    return None
 
 
 def copy_calibration():
