@@ -40,7 +40,8 @@
 namespace {
 
 constexpr int FT = 256;      // threads per workgroup (4 waves)
-constexpr int TJ = 256;      // sources per LDS tile
+constexpr int TJ = 512;      // sources per LDS tile (two per thread)
+constexpr int LC = FT;       // particle-list leaves per chunk (one per thread)
 
 template <typename R> struct V4;
 template <> struct V4<float> { using T = float4; };
@@ -205,8 +206,8 @@ template <typename R, bool POT, bool ZERO_EPS, bool COLL>
 __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevState d, uint32_t ng) {
     using T4 = typename V4<R>::T;
     __shared__ T4 tile[TJ + 16];
-    __shared__ uint32_t lbeg[TJ];
-    __shared__ uint32_t lscan[TJ + 1];
+    __shared__ uint32_t lbeg[LC];
+    __shared__ uint32_t lscan[LC + 1];
     __shared__ R red[4][4][64];
     __shared__ uint32_t s_item;
     __shared__ uint32_t wsum[4];
@@ -336,16 +337,16 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
             // ---- node list: centre of mass and mass of each accepted node
             for (uint32_t t0 = 0; t0 < npc; t0 += TJ) {
                 const uint32_t cntt = min((uint32_t)TJ, npc - t0);
-                if ((uint32_t)tid < cntt) {
-                    const double4 m = d.nd_mom[d.pc_pool[pc0 + t0 + tid]];
-                    tile[tid] = mk4<R>((R)(m.x - cen.x), (R)(m.y - cen.y), (R)(m.z - cen.z), (R)(eqm ? m.w / m0 : m.w));
+                for (uint32_t e = tid; e < cntt; e += FT) {
+                    const double4 m = d.nd_mom[d.pc_pool[pc0 + t0 + e]];
+                    tile[e] = mk4<R>((R)(m.x - cen.x), (R)(m.y - cen.y), (R)(m.z - cen.z), (R)(eqm ? m.w / m0 : m.w));
                 }
                 compute_tile(cntt, false);
             }
 
             // ---- particle list: the particles of each listed leaf
-            for (uint32_t l0 = 0; l0 < npp; l0 += TJ) {
-                const uint32_t nl = min((uint32_t)TJ, npp - l0);
+            for (uint32_t l0 = 0; l0 < npp; l0 += LC) {
+                const uint32_t nl = min((uint32_t)LC, npp - l0);
                 uint32_t lc = 0, lb = 0;
                 if ((uint32_t)tid < nl) {
                     const uint32_t leaf = d.pp_pool[pp0 + l0 + tid];
@@ -367,8 +368,8 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                 __syncthreads();
                 for (uint32_t p0 = 0; p0 < tot; p0 += TJ) {
                     const uint32_t cntt = min((uint32_t)TJ, tot - p0);
-                    if ((uint32_t)tid < cntt) {
-                        const uint32_t f = p0 + tid;
+                    for (uint32_t e = tid; e < cntt; e += FT) {
+                        const uint32_t f = p0 + e;
                         uint32_t lo = 0, hi = nl - 1;          // last k with lscan[k] <= f
                         while (lo < hi) {
                             const uint32_t mid = (lo + hi + 1) >> 1;
@@ -376,8 +377,8 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                         }
                         const uint32_t j = lbeg[lo] + (f - lscan[lo]);
                         const double4 q = d.pos[j];
-                        tile[tid] = mk4<R>((R)(q.x - cen.x), (R)(q.y - cen.y), (R)(q.z - cen.z), (R)q.w);
-                        if (COLL) jidx[tid] = j;
+                        tile[e] = mk4<R>((R)(q.x - cen.x), (R)(q.y - cen.y), (R)(q.z - cen.z), (R)q.w);
+                        if (COLL) jidx[e] = j;
                     }
                     compute_tile(cntt, true);
                 }
