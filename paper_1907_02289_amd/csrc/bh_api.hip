@@ -52,7 +52,7 @@ struct bh_ctx {
 
     // device buffers
     DevBuf sys_off_b, sys_tab_b, acc_tab_b, box_b, box_part_b, sys_m0_b;
-    DevBuf pos_in, vel_in, idx_in, pos, vel, acc, idx;
+    DevBuf pos_in, vel_in, idx_in, pos, vel, acc, idx, inv;
     DevBuf key, key_tmp, val, val_tmp, hist, scan_tmp;
     DevBuf nd_prefix, nd_begin, nd_count, nd_first, nd_meta, nd_walk, nd_mom, nd_quad, tmp_a, tmp_b;
     DevBuf gmark, grp, g_lo, g_hi, g_cen, g_pc_off, g_pc_len, g_pp_off, g_pp_len, g_cost, order;
@@ -172,6 +172,7 @@ void refresh_state(bh_ctx *c) {
     d.vel = P<double4>(c->vel);
     d.acc = P<double4>(c->acc);
     d.idx = P<uint32_t>(c->idx);
+    d.inv = P<uint32_t>(c->inv);
     d.key = P<uint64_t>(c->key);
     d.key_tmp = P<uint64_t>(c->key_tmp);
     d.val = P<uint32_t>(c->val);
@@ -306,6 +307,7 @@ bh_status ensure_particles(bh_ctx *c, uint32_t n) {
     HIPCHK(c, grow(c->vel, d4));
     HIPCHK(c, grow(c->acc, d4));
     HIPCHK(c, grow(c->idx, u4));
+    HIPCHK(c, grow(c->inv, u4));
     HIPCHK(c, grow(c->key, u8));
     HIPCHK(c, grow(c->key_tmp, u8));
     HIPCHK(c, grow(c->val, u4));
@@ -634,7 +636,7 @@ bh_status bh_destroy(bh_ctx *c) {
     if (!c) return BH_EINVAL;
     (void)hipDeviceSynchronize();
     DevBuf *all[] = {&c->sys_off_b, &c->sys_tab_b, &c->acc_tab_b, &c->box_b, &c->box_part_b, &c->sys_m0_b, &c->pos_in,
-                     &c->vel_in, &c->idx_in, &c->pos, &c->vel, &c->acc, &c->idx, &c->key, &c->key_tmp,
+                     &c->vel_in, &c->idx_in, &c->pos, &c->vel, &c->acc, &c->idx, &c->inv, &c->key, &c->key_tmp,
                      &c->val, &c->val_tmp, &c->hist, &c->scan_tmp, &c->nd_prefix, &c->nd_begin, &c->nd_count,
                      &c->nd_first, &c->nd_meta, &c->nd_walk, &c->nd_mom, &c->nd_quad, &c->tmp_a, &c->tmp_b,
                      &c->gmark, &c->grp, &c->g_lo, &c->g_hi, &c->g_cen, &c->g_pc_off, &c->g_pc_len,

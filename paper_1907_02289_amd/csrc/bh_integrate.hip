@@ -55,10 +55,13 @@ __global__ void k_kick(double4 *vel, const double4 *acc, uint32_t n, double h) {
     }
 }
 
+// Results back in caller order, walked in caller order: the writes to the
+// caller's arrays are coalesced and the reads of the sorted state gather
+// through the inverse permutation.
 __global__ void k_scatter_state(DevState d) {
     uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += stride) {
-        uint32_t gi = d.idx[j];
+    for (uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x; gi < d.n; gi += stride) {
+        const uint32_t j = d.inv[gi];
         int s = sys_of(d.sys_off, d.n_sys, gi);
         uint32_t k = gi - d.sys_off[s];
         SysPtr p = d.sys_tab[s];
@@ -76,8 +79,8 @@ __global__ void k_scatter_state(DevState d) {
 
 __global__ void k_scatter_acc(DevState d, const bhk::AccPtr *tab) {
     uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += stride) {
-        uint32_t gi = d.idx[j];
+    for (uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x; gi < d.n; gi += stride) {
+        const uint32_t j = d.inv[gi];
         int s = sys_of(d.sys_off, d.n_sys, gi);
         uint32_t k = gi - d.sys_off[s];
         bhk::AccPtr p = tab[s];

@@ -142,6 +142,7 @@ struct DevState {
     uint32_t *idx_in;
     double4 *pos, *vel, *acc;      // sorted: (x,y,z,m), (vx,vy,vz,0), (ax,ay,az,pot)
     uint32_t *idx;                 // sorted slot -> global caller index
+    uint32_t *inv;                 // global caller index -> sorted slot (the inverse of idx)
     uint64_t *key, *key_tmp;
     uint32_t *val, *val_tmp, *hist, *scan_tmp;
     // tree

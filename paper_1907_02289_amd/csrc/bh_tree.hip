@@ -214,7 +214,9 @@ __global__ void k_permute(DevState d) {
         uint32_t src = d.val[j];
         d.pos[j] = d.pos_in[src];
         d.vel[j] = d.vel_in[src];
-        d.idx[j] = d.idx_in[src];
+        const uint32_t gi = d.idx_in[src];
+        d.idx[j] = gi;
+        d.inv[gi] = j;
         if (d.amag && d.amag_in) d.amag[j] = d.amag_in[src];
     }
 }
