@@ -841,9 +841,11 @@ bh_status bh_step_continue(bh_ctx *c, double dt, int32_t n_steps, int32_t rebuil
 
 bh_status bh_direct_sum(bh_ctx *c, const bh_system *sys, const int64_t *targets, int64_t n_targets, double *ax,
                         double *ay, double *az, void *stream) {
-    if (!c || !sys || !targets || !ax || !ay || !az) return BH_EINVAL;
+    if (!c || !sys) return BH_EINVAL;
     if (sys->n < 1 || !sys->x || !sys->y || !sys->z || !sys->m || n_targets < 0 || sys->n >= (1ll << 31))
         return fail(c, BH_EINVAL, "bh_direct_sum: bad system or targets");
+    if (n_targets > 0 && (!targets || !ax || !ay || !az))
+        return fail(c, BH_EINVAL, "bh_direct_sum: null target or output array");
     const bool coll = c->P.r_coll > 0.0;
     if (coll && (!sys->vx || !sys->vy || !sys->vz))
         return fail(c, BH_EINVAL, "bh_direct_sum: the collision branch needs velocities");

@@ -231,6 +231,37 @@ def test_nonfinite_rejected(torch_cuda):
     ctx.close()
 
 
+def test_empty_inputs_rejected_and_context_recovers(torch_cuda):
+    """No system, or an empty one (alone or beside a valid one): BH_EINVAL
+    before any device work; zero direct-sum targets: nothing to do; the
+    context then still builds and evaluates a valid system correctly."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    ctx = _ctx(0.5, 1e-3)
+    empty = {k: torch.zeros(0, dtype=torch.float64, device="cuda") for k in ("x", "y", "z", "vx", "vy", "vz", "m")}
+    s = inputs.ring(1000, 17)
+    dev = bh.to_device(s)
+    for systems in ([], [empty], [dev, empty]):
+        with pytest.raises(bh.BHError) as e:
+            ctx.build_tree(systems)
+        assert e.value.status == bh.BH_EINVAL
+    with pytest.raises(bh.BHError) as e:
+        ctx.make_lists()
+    assert e.value.status == bh.BH_ESTATE
+    none = {k: torch.zeros(0, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+    ctx.direct_sum(dev, torch.zeros(0, dtype=torch.int64, device="cuda"), none)
+    ctx.build_tree([dev])
+    ctx.make_lists()
+    out = {k: torch.zeros(s.n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+    ctx.forces([out])
+    torch.cuda.synchronize()
+    ax, ay, az, _, mag, _ = oracle.bh_accel(s.x, s.y, s.z, s.m, 0.5, 1e-3)
+    err = np.sqrt((out["ax"].cpu().numpy() - ax) ** 2 + (out["ay"].cpu().numpy() - ay) ** 2
+                  + (out["az"].cpu().numpy() - az) ** 2)
+    assert np.all(err <= 1e-12 * mag)
+    ctx.close()
+
+
 def test_step_fp64_matches_oracle_trajectory(torch_cuda):
     """KDK with list reuse (rebuild every 3 steps) against the oracle's
     trajectory: FP64 forces agree to ~1e-13, so positions stay within 1e-10."""
