@@ -9,7 +9,14 @@
 // of the group's particles and of every source are taken relative to the
 // group centre in FP64 and only then rounded to FP32; the pair terms and
 // their sums are FP32, the result is scaled by G and written in FP64.  The
-// FP64 variant is the same loop in double precision.
+// FP64 variant is the same loop in double precision.  In FP32, a system
+// whose particles all have one mass m0 (the paper's ring particles) enters
+// the particle-pair loop with unit masses and its node masses in units of
+// m0, the sums being scaled by G m0 at the end: one multiply fewer per pair.
+//
+// Sources are staged 512 at a time in LDS as group-relative float4 (x, y,
+// z, m); particle-list leaves are read 256 at a time and their particles
+// located in the tile by a prefix sum over the leaf sizes.
 //
 // Scheduling (Sec. 4.6): a persistent grid takes groups from an atomic
 // queue in order of decreasing interaction count, so the longest lists start
