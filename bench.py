@@ -259,7 +259,7 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "repeats": 3}))
 
 
-def cpu_baseline(system, theta, n_grp, eps, rebuild_every, cyl_radius=0.0, n_sample_groups=1024, seed=0):
+def cpu_baseline(system, theta, n_grp, eps, rebuild_every, cyl_radius=0.0, n_sample_groups=16384, seed=0):
     """The oracle on the host cores: full tree build of the same ring (in the
     tuned path's tree coordinates), then walk + forces for a random sample of
     groups; interactions of the sample over the time of the sample's work
