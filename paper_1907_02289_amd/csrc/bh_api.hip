@@ -48,7 +48,7 @@ struct bh_ctx {
     // capacities
     uint32_t n_cap = 0, node_cap = 0, sys_cap = 0;
     uint64_t pc_cap = 0, pp_cap = 0;
-    uint32_t walk_waves = 0, walk_front = 4096, walk_list = 8192;
+    uint32_t walk_waves = 0, walk_waves_net = 0, walk_front = 4096, walk_list = 8192;
 
     // device buffers
     DevBuf sys_off_b, sys_tab_b, acc_tab_b, box_b, box_part_b, sys_m0_b;
@@ -209,6 +209,7 @@ void refresh_state(bh_ctx *c) {
     d.walk_front_cap = c->walk_front;
     d.walk_list_cap = c->walk_list;
     d.walk_waves = c->walk_waves;
+    d.walk_waves_net = c->walk_waves_net;
     d.cnt = P<DevCounters>(c->counters);
     const bool learned = c->P.criterion == BH_OPEN_LEARNED;
     d.walk_mode = c->walk_mode;
@@ -378,12 +379,14 @@ bh_status ensure_nodes(bh_ctx *c, uint32_t cap) {
 }
 
 bh_status ensure_walk(bh_ctx *c) {
-    // at most 4 GiB of walk scratch: fewer walking waves when each needs more
+    // at most 4 GiB of walk scratch: fewer walking waves when each needs more.
+    // The geometric walk keeps 24 waves per CU resident, the walk with the
+    // network in it (twice the registers) 16.
     const size_t per_wave = 2 * (size_t)c->walk_front + 2 * (size_t)c->walk_list;
-    size_t waves = ((size_t)1 << 30) / per_wave;
-    waves = std::min<size_t>(waves, (size_t)c->n_cu * 16);
-    waves = std::max<size_t>(waves, 64) & ~(size_t)3;
-    c->walk_waves = (uint32_t)waves;
+    const size_t cap = ((size_t)1 << 30) / per_wave;
+    c->walk_waves = (uint32_t)(std::max<size_t>(std::min<size_t>(cap, (size_t)c->n_cu * 24), 64) & ~(size_t)3);
+    c->walk_waves_net = (uint32_t)(std::max<size_t>(std::min<size_t>(cap, (size_t)c->n_cu * 16), 64) & ~(size_t)3);
+    c->walk_waves_net = std::min(c->walk_waves_net, c->walk_waves);
     size_t words = (size_t)c->walk_waves * per_wave;
     HIPCHK(c, grow(c->walk_scratch, words * 4));
     return BH_OK;
@@ -614,7 +617,8 @@ bh_status bh_create(bh_ctx **out, const bh_params *p) {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
         c->n_cu = ncu;
-    c->walk_waves = (uint32_t)c->n_cu * 16;
+    c->walk_waves = (uint32_t)c->n_cu * 24;
+    c->walk_waves_net = (uint32_t)c->n_cu * 16;
     bool ok = hipHostMalloc((void **)&c->h_cnt, sizeof(DevCounters)) == hipSuccess &&
               hipEventCreateWithFlags(&c->tab_ev, hipEventDisableTiming) == hipSuccess &&
               grow(c->counters, sizeof(DevCounters)) == hipSuccess;

@@ -167,6 +167,7 @@ struct DevState {
     unsigned long long pc_cap, pp_cap;
     uint32_t *walk_scratch;        // per walking wave: 2 frontiers + 2 lists
     uint32_t walk_front_cap, walk_list_cap, walk_waves;
+    uint32_t walk_waves_net;       // walking waves of the learned and enumerating rules
     DevCounters *cnt;
     // learned opening rule
     int walk_mode;                 // WALK_GEOMETRIC, WALK_LEARNED, WALK_ENUMERATE

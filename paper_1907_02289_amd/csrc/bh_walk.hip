@@ -94,7 +94,7 @@ __device__ __forceinline__ bool decide(const DevState &d, const GroupCtx &gc, ui
 }
 
 template <bool GEO>
-__global__ void __launch_bounds__(WALK_TPB) k_walk(DevState d) {
+__global__ void __launch_bounds__(WALK_TPB, (GEO ? 6 : 1)) k_walk(DevState d) {
     const uint32_t wave = (blockIdx.x * WALK_TPB + threadIdx.x) >> 6;
     if (wave >= d.walk_waves) return;
     const int lane = __lane_id();
@@ -262,7 +262,8 @@ namespace bhk {
 
 void walk(const DevState &d, hipStream_t s) {
     k_walk_reset<<<1, 64, 0, s>>>(d);
-    unsigned blocks = (d.walk_waves * 64 + WALK_TPB - 1) / WALK_TPB;
+    const uint32_t waves = d.walk_mode == WALK_GEOMETRIC ? d.walk_waves : d.walk_waves_net;
+    unsigned blocks = (waves * 64 + WALK_TPB - 1) / WALK_TPB;
     if (d.walk_mode == WALK_GEOMETRIC)
         k_walk<true><<<blocks, WALK_TPB, 0, s>>>(d);
     else
