@@ -39,6 +39,7 @@ struct bh_ctx {
     // host-side sizes of the current build
     int n_sys = 0;
     uint32_t n = 0;
+    uint32_t box_blocks = 1;
     std::vector<uint32_t> sys_off;
     bool tree_valid = false, lists_valid = false;
     uint32_t n_nodes = 0, n_groups = 0, max_level = 0;
@@ -164,6 +165,7 @@ void refresh_state(bh_ctx *c) {
     d.sys_tab = P<SysPtr>(c->sys_tab_b);
     d.box = P<double4>(c->box_b);
     d.box_part = P<double>(c->box_part_b);
+    d.box_blocks = c->box_blocks;
     d.sys_m0 = P<double>(c->sys_m0_b);
     d.pos_in = P<double4>(c->pos_in);
     d.vel_in = P<double4>(c->vel_in);
@@ -285,7 +287,6 @@ bh_status ensure_systems(bh_ctx *c, int n_sys) {
     HIPCHK(c, grow(c->sys_tab_b, cap * sizeof(SysPtr)));
     HIPCHK(c, grow(c->acc_tab_b, cap * sizeof(bhk::AccPtr)));
     HIPCHK(c, grow(c->box_b, cap * sizeof(double4)));
-    HIPCHK(c, grow(c->box_part_b, (size_t)cap * BOX_BLOCKS * 8 * sizeof(double)));
     HIPCHK(c, grow(c->sys_m0_b, cap * sizeof(double)));
     if (c->h_systab) (void)hipHostFree(c->h_systab);
     if (c->h_acctab) (void)hipHostFree(c->h_acctab);
@@ -591,6 +592,11 @@ bh_status set_systems(bh_ctx *c, const bh_system *sys, int32_t n_sys, hipStream_
     HIPCHK(c, hipMemcpyAsync(c->sys_off_b.p, h_off, (n_sys + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipEventRecord(c->tab_ev, s));
     c->tab_ev_pending = true;
+    // root-box partials: one system alone fills the chip, and the partials
+    // stay O(n / BOX_PER_BLOCK) however the particles split into systems
+    const uint64_t per = (total + (uint64_t)n_sys - 1) / (uint64_t)n_sys;
+    c->box_blocks = (uint32_t)std::min<uint64_t>(BOX_BLOCKS_MAX, std::max<uint64_t>(1, per / BOX_PER_BLOCK));
+    HIPCHK(c, grow(c->box_part_b, (size_t)n_sys * c->box_blocks * 8 * sizeof(double)));
     STCHK(ensure_particles(c, c->n));
     if (c->node_cap < c->n + (uint32_t)n_sys) STCHK(ensure_nodes(c, c->n + n_sys + 1024));
     if (!c->pc_pool.p) STCHK(ensure_pools(c, (uint64_t)c->n * 8 + 65536, (uint64_t)c->n * 2 + 65536));

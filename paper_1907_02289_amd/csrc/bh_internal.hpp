@@ -135,7 +135,8 @@ struct DevState {
     const uint32_t *sys_off;       // [n_sys+1]
     const SysPtr *sys_tab;         // [n_sys]
     double4 *box;                  // [n_sys]: lo x, y, z, 2^21 / S
-    double *box_part;              // [n_sys][BOX_BLOCKS][8]: min, max of the tree coordinates and of the mass
+    double *box_part;              // [n_sys][box_blocks][8]: min, max of the tree coordinates and of the mass
+    uint32_t box_blocks;           // root-box partial blocks per system (1..BOX_BLOCKS_MAX)
     double *sys_m0;                // [n_sys] the common particle mass of a system, 0 when masses differ
     // particles: input order of the current build and sorted order
     double4 *pos_in, *vel_in;
@@ -191,7 +192,9 @@ struct DevState {
 
 enum { WALK_GEOMETRIC = 0, WALK_LEARNED = 1, WALK_ENUMERATE = 2 };
 
-constexpr int BOX_BLOCKS = 64;
+// root-box reduction: blocks per system, at most BOX_BLOCKS_MAX, about
+// BOX_PER_BLOCK particles each for the average system
+constexpr uint32_t BOX_BLOCKS_MAX = 1024, BOX_PER_BLOCK = 1024;
 
 // ---------------------------------------------------------------- host launchers
 namespace bhk {

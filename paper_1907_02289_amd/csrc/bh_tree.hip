@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(TPB) k_box_partial(DevState d) {
     // per axis 0..2 the tree coordinates, axis 3 the mass
     double lo[4] = {INFINITY, INFINITY, INFINITY, INFINITY}, hi[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
     bool bad = false;
-    for (uint32_t i = b0 + blockIdx.x * TPB + threadIdx.x; i < b1; i += BOX_BLOCKS * TPB) {
+    for (uint32_t i = b0 + blockIdx.x * TPB + threadIdx.x; i < b1; i += d.box_blocks * TPB) {
         const double4 p = d.pos_in[i];
         bad |= !isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z);
         double c[4];
@@ -142,25 +142,30 @@ __global__ void __launch_bounds__(TPB) k_box_partial(DevState d) {
         int a = threadIdx.x;
         double v = red[0][a];
         for (int k = 1; k < TPB / 64; ++k) v = (a < 4) ? fmin(v, red[k][a]) : fmax(v, red[k][a]);
-        d.box_part[((size_t)s * BOX_BLOCKS + blockIdx.x) * 8 + a] = v;
+        d.box_part[((size_t)s * d.box_blocks + blockIdx.x) * 8 + a] = v;
     }
 }
 
 __global__ void k_box_final(DevState d) {
+    // one wave per system: lanes stride over the partials, then a wave reduction
     const int s = blockIdx.x;
-    if (threadIdx.x != 0) return;
     double lo[4], hi[4];
     for (int a = 0; a < 4; ++a) {
         lo[a] = INFINITY;
         hi[a] = -INFINITY;
     }
-    for (int b = 0; b < BOX_BLOCKS; ++b) {
-        const double *p = d.box_part + ((size_t)s * BOX_BLOCKS + b) * 8;
+    for (uint32_t b = threadIdx.x; b < d.box_blocks; b += 64) {
+        const double *p = d.box_part + ((size_t)s * d.box_blocks + b) * 8;
         for (int a = 0; a < 4; ++a) {
             lo[a] = fmin(lo[a], p[a]);
             hi[a] = fmax(hi[a], p[4 + a]);
         }
     }
+    for (int a = 0; a < 4; ++a) {
+        lo[a] = wave_min(lo[a]);
+        hi[a] = wave_max(hi[a]);
+    }
+    if (threadIdx.x != 0) return;
     // equal-mass systems let the force kernel take the common mass out of the pair loop
     d.sys_m0[s] = (lo[3] == hi[3] && lo[3] > 0.0) ? lo[3] : 0.0;
     if (d.cyl_r > 0.0) {
@@ -495,7 +500,7 @@ void load_systems(const DevState &d, hipStream_t s) {
 }
 
 void root_box_keys(const DevState &d, hipStream_t s) {
-    k_box_partial<<<dim3(BOX_BLOCKS, d.n_sys), TPB, 0, s>>>(d);
+    k_box_partial<<<dim3(d.box_blocks, d.n_sys), TPB, 0, s>>>(d);
     k_box_final<<<d.n_sys, 64, 0, s>>>(d);
     k_keys<<<grid_for(d.n), TPB, 0, s>>>(d);
     radix_sort(d.key, d.val, d.key_tmp, d.val_tmp, d.n, 0, 63, d.hist, d.scan_tmp, s, d.sys_off, d.n_sys);
