@@ -225,7 +225,9 @@ bh_status bh_step_continue(bh_ctx *ctx, double dt, int32_t n_steps, int32_t rebu
  *   a[t] = sum_j G m_j (x_j - x_i) / (|x_j - x_i|^2 + eps^2)^(3/2),
  * j over all n particles of sys (caller order; j = i adds nothing when
  * eps > 0 and is skipped when eps = 0).  targets, ax, ay, az: device arrays
- * of n_targets entries (may be NULL when n_targets is 0: nothing is done).  Uses the context's G and eps; independent of the
+ * of n_targets entries (may be NULL when n_targets is 0: nothing is done).
+ * A target index outside [0, n) yields NaN in its three outputs; no memory
+ * outside the arrays is read.  Uses the context's G and eps; independent of the
  * tree.  Serves as the error judge of the approximation.  With r_coll > 0
  * every pair follows Eq. (2) with both branches (see bh_params) and sys
  * must carry velocities. */

@@ -437,6 +437,8 @@ bh_status rebuild(bh_ctx *c, hipStream_t s, bool from_caller) {
             return fail(c, BH_EINVAL, "cylindrical tree: radial or vertical extent exceeds 2 pi cyl_radius");
         }
         if (c->h_cnt->flags[FLAG_NODE_OVF]) {
+            // node ids are 32-bit: the capacity doubles at most up to 2^32 - 1
+            if (c->node_cap >= 0x80000000u) return fail(c, BH_ECAPACITY, "tree node capacity cannot grow further");
             STCHK(ensure_nodes(c, c->node_cap * 2));
             refresh_state(c);
             continue;
@@ -820,16 +822,20 @@ bh_status bh_step(bh_ctx *c, const bh_system *sys, int32_t n_sys, double dt, int
     for (int k = 0; sys && k < n_sys; ++k)
         if (!sys[k].vx || !sys[k].vy || !sys[k].vz) return fail(c, BH_EINVAL, "bh_step needs velocities");
     hipStream_t s = (hipStream_t)stream;
-    ev_begin(c, EV_STEP, s);
     c->tree_valid = c->lists_valid = c->state_valid = false;
-    STCHK(set_systems(c, sys, n_sys, s));
-    STCHK(rebuild(c, s, true));
-    STCHK(make_lists(c, s));
-    refresh_state(c);
-    STCHK(run_forces(c, s, false));
-    c->have_vel = true;
-    c->state_valid = true;
-    bh_status st = integrate(c, dt, n_steps, rebuild_every, s);
+    // the step event pair stays balanced on every return
+    auto body = [&]() -> bh_status {
+        STCHK(set_systems(c, sys, n_sys, s));
+        STCHK(rebuild(c, s, true));
+        STCHK(make_lists(c, s));
+        refresh_state(c);
+        STCHK(run_forces(c, s, false));
+        c->have_vel = true;
+        c->state_valid = true;
+        return integrate(c, dt, n_steps, rebuild_every, s);
+    };
+    ev_begin(c, EV_STEP, s);
+    bh_status st = body();
     if (st != BH_OK) c->state_valid = false;
     ev_end(c, EV_STEP, s);
     return st;

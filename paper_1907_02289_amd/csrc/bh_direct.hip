@@ -29,8 +29,11 @@ __global__ void __launch_bounds__(DT) k_direct_part(const double *x, const doubl
     const bool ton = t < nt;
     int64_t i = 0;
     double xi = 0, yi = 0, zi = 0;
+    bool bad = false;             // a target index outside [0, n): NaN result, nothing read out of range
     if (ton) {
         i = targets[t];
+        bad = i < 0 || i >= n;
+        if (bad) i = 0;
         xi = x[i];
         yi = y[i];
         zi = z[i];
@@ -88,7 +91,7 @@ __global__ void __launch_bounds__(DT) k_direct_part(const double *x, const doubl
     if (w == 0 && ton) {
         double *o = part + ((size_t)blockIdx.y * nt + t) * NC;
         for (int a = 0; a < NC; ++a)
-            o[a] = ((red[a][0][lane] + red[a][1][lane]) + red[a][2][lane]) + red[a][3][lane];
+            o[a] = bad ? NAN : ((red[a][0][lane] + red[a][1][lane]) + red[a][2][lane]) + red[a][3][lane];
     }
 }
 

@@ -262,6 +262,69 @@ def test_empty_inputs_rejected_and_context_recovers(torch_cuda):
     ctx.close()
 
 
+def test_size_limits_and_the_most_systems(torch_cuda):
+    """Limits of bh_build_tree: 65536 systems, or 2^31 particles in all, are
+    BH_EINVAL before any device work (the counts are checked, the arrays are
+    never read); 65535 systems of 1-4 particles then build and evaluate in
+    one launch per stage.  A system that small is one leaf and one group, so
+    its Barnes-Hut force is its direct sum: FP64 within 1e-12 of the sum of
+    the term magnitudes, against the oracle's direct sum per system."""
+    import ctypes
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log("[gpu] size limits, 65535 systems")
+    ctx = _ctx(0.5, 1e-3)
+    one = torch.zeros(1, dtype=torch.float64, device="cuda")
+    p = ctypes.c_void_p(one.data_ptr())
+
+    def raw(counts):
+        arr = (bh.System * len(counts))()
+        for k, n in enumerate(counts):
+            arr[k].n = n
+            for f in ("x", "y", "z", "vx", "vy", "vz", "m"):
+                setattr(arr[k], f, p)
+        return ctx.L.bh_build_tree(ctx.h, arr, len(counts), bh._stream())
+
+    assert raw([1] * 65536) == bh.BH_EINVAL
+    assert raw([2 ** 30, 2 ** 30]) == bh.BH_EINVAL
+    assert raw([2 ** 31]) == bh.BH_EINVAL
+    assert raw([2 ** 40, 1]) == bh.BH_EINVAL
+    assert raw([5, -1]) == bh.BH_EINVAL
+    torch.cuda.synchronize()
+
+    rng = np.random.default_rng(23)
+    sizes = rng.integers(1, 5, 65535)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    n = int(off[-1])
+    x, y, z = (rng.normal(0.0, 1.0, n) for _ in range(3))
+    m = rng.uniform(0.5, 1.5, n) / n
+    cols = {k: torch.as_tensor(v, device="cuda") for k, v in (("x", x), ("y", y), ("z", z), ("m", m))}
+    acc = {k: torch.zeros(n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+    systems = [{k: t[off[i]:off[i + 1]] for k, t in cols.items()} for i in range(sizes.size)]
+    outs = [{k: t[off[i]:off[i + 1]] for k, t in acc.items()} for i in range(sizes.size)]
+    ctx.build_tree(systems)
+    ctx.make_lists()
+    ctx.forces(outs)
+    torch.cuda.synchronize()
+    assert ctx.query()["n_groups"] == sizes.size
+    g = {k: v.cpu().numpy() for k, v in acc.items()}
+    want = np.zeros((3, n))
+    mag = np.zeros(n)
+    for i in range(sizes.size):
+        a, b = off[i], off[i + 1]
+        ax, ay, az, _ = oracle.direct(x[a:b], y[a:b], z[a:b], m[a:b], 1e-3)
+        want[:, a:b] = ax, ay, az
+        d = np.stack([x[a:b], y[a:b], z[a:b]], 1)
+        dv = d[None, :, :] - d[:, None, :]
+        r2 = (dv ** 2).sum(-1) + 1e-6
+        mag[a:b] = (m[a:b][None, :] * np.sqrt((dv ** 2).sum(-1)) / r2 ** 1.5).sum(1)
+    err = np.sqrt((g["ax"] - want[0]) ** 2 + (g["ay"] - want[1]) ** 2 + (g["az"] - want[2]) ** 2)
+    single = (sizes == 1)[np.repeat(np.arange(sizes.size), sizes)]
+    assert np.all(err[single] == 0.0)
+    assert np.all(err <= 1e-12 * mag)
+    ctx.close()
+
+
 def test_step_fp64_matches_oracle_trajectory(torch_cuda):
     """KDK with list reuse (rebuild every 3 steps) against the oracle's
     trajectory: FP64 forces agree to ~1e-13, so positions stay within 1e-10."""
@@ -298,6 +361,28 @@ def test_direct_sum_judge_matches_oracle(torch_cuda):
     g = {k: v.cpu().numpy() for k, v in out.items()}
     err = np.sqrt((g["ax"] - ax) ** 2 + (g["ay"] - ay) ** 2 + (g["az"] - az) ** 2)
     assert np.all(err <= 1e-13 * np.sqrt(ax ** 2 + ay ** 2 + az ** 2))
+    ctx.close()
+
+
+def test_direct_sum_target_out_of_range_gives_nan(torch_cuda):
+    """Target indices outside [0, n) are caught by the kernel itself: NaN in
+    their outputs, the other targets as the oracle gives them."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log("[gpu] direct sum, targets out of range")
+    s = inputs.ring(3000, 18)
+    tg = np.array([5, -1, 2999, 3000, 0, -(2 ** 40), 1234], np.int64)
+    ctx = _ctx(0.5, 1e-3)
+    dev = bh.to_device(s)
+    out = {k: torch.zeros(tg.size, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+    ctx.direct_sum(dev, torch.as_tensor(tg, device="cuda"), out)
+    torch.cuda.synchronize()
+    g = np.stack([out[k].cpu().numpy() for k in ("ax", "ay", "az")])
+    bad = (tg < 0) | (tg >= s.n)
+    assert np.all(np.isnan(g[:, bad]))
+    ax, ay, az, _ = oracle.direct(s.x, s.y, s.z, s.m, 1e-3, targets=tg[~bad])
+    want = np.stack([ax, ay, az])
+    assert np.all(np.abs(g[:, ~bad] - want) <= 1e-13 * np.abs(want).max(0))
     ctx.close()
 
 
