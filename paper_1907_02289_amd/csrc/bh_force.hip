@@ -229,6 +229,8 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
     // detection margin: a bound on how far FP32 (FP64) rounding of the
     // group-relative coordinates can move a squared distance
     constexpr double U = sizeof(R) == 4 ? 0x1p-20 : 0x1p-49;
+    // tail mode (below) in the FP32 kernels without the collision branch
+    constexpr bool TAIL = sizeof(R) == 4 && !COLL;
 
     for (;;) {
         if (tid == 0) s_item = atomicAdd(&d.cnt->work_counter2, 1u);
@@ -246,6 +248,7 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
         const double m0 = sizeof(R) == 4 ? d.sys_m0[gi.sys] : 0.0;
         const bool eqm = m0 > 0.0;
         const double gscale = eqm ? d.G * m0 : d.G;
+        const double inv_m0 = eqm ? 1.0 / m0 : 1.0;
         const unsigned long long pc0 = d.g_pc_off[g], pp0 = d.g_pp_off[g];
         const uint32_t npc = d.g_pc_len[g], npp = d.g_pp_len[g];
 
@@ -256,17 +259,29 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
             // of at most 32 (16) particles -- a small group, or the last chunk
             // of a larger one -- spreads its wave over 2 (4) sub-slices of its
             // source range: cw lanes per particle, sub = 64 / cw parts.
+            // split, sub and cw are powers of two: their divisions are shifts
             const int n_ic = (int)((nb + 63) >> 6);
-            const int split = 4 / n_ic;
+            const int split_sh = n_ic == 1 ? 2 : (n_ic == 2 ? 1 : 0);
+            const int split = 1 << split_sh;                         // 4 / n_ic
             const int ichunk = w % n_ic;
             const int jslice = w / n_ic;
             const bool wave_on = jslice < split;
             const int cnt_w = min(64, (int)nb - 64 * ichunk);
-            const int cw = cnt_w <= 16 ? 16 : (cnt_w <= 32 ? 32 : 64);
-            const int sub = 64 / cw;
-            const int part = lane / cw;
-            const bool any_sub = (int)nb - 64 * (n_ic - 1) <= 32;   // the block's last chunk is sub-sliced
-            const uint32_t il = 64 * ichunk + lane % cw;
+            const int cw_sh = cnt_w <= 16 ? 4 : (cnt_w <= 32 ? 5 : 6);
+            const int cw = 1 << cw_sh;
+            const int sub_sh = 6 - cw_sh;
+            const int sub = 1 << sub_sh;                             // 64 / cw
+            const int part = lane >> cw_sh;
+            // A chunk of 33 to 48 particles runs in tail mode: lanes 0..47 hold
+            // the particles and take the first three quarters of the wave's
+            // source range; lanes 48..63 take the last quarter for the three
+            // 16-particle slices in turn and hand each slice's partial sums to
+            // the lanes that own them.  Every lane then runs 3/4 of the range
+            // instead of a full wave running all of it.
+            const bool tailm = TAIL && cnt_w > 32 && cnt_w <= 48;
+            const int last_cnt = (int)nb - 64 * (n_ic - 1);
+            const bool any_sub = last_cnt <= (TAIL ? 48 : 32);       // the block's last chunk is sub-sliced or tailed
+            const uint32_t il = 64 * ichunk + (lane & (cw - 1));
             const bool ion = wave_on && il < nb;
             const uint32_t i = gi.begin + ib + il;
             R xi = 0, yi = 0, zi = 0;
@@ -294,18 +309,18 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
             // the collision branch applies to).
             auto compute_tile = [&](uint32_t cntt, bool particles) {
                 const int ct = (int)cntt;
-                const int cntp = any_sub ? (ct + 4 * split - 1) / (4 * split) * (4 * split) : ct;
+                const int cntp = any_sub ? ((ct + (4 << split_sh) - 1) >> (2 + split_sh)) << (2 + split_sh) : ct;
                 for (int t = ct + tid; t < cntp; t += FT) tile[t] = mk4<R>((R)1e18, (R)1e18, (R)1e18, (R)0);
                 __syncthreads();
                 if (wave_on) {
                     int jb, je;
                     if (any_sub) {
                         const int q = cntp >> 2;
-                        jb = 4 * (q * jslice / split);
-                        je = 4 * (q * (jslice + 1) / split);
+                        jb = 4 * ((q * jslice) >> split_sh);
+                        je = 4 * ((q * (jslice + 1)) >> split_sh);
                     } else {
-                        jb = ct * jslice / split;
-                        je = ct * (jslice + 1) / split;
+                        jb = (ct * jslice) >> split_sh;
+                        je = (ct * (jslice + 1)) >> split_sh;
                     }
                     // this lane's part of the range: [jl0, jl0 + L)
                     int jl0, L;
@@ -313,7 +328,7 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                         jl0 = jb;
                         L = max(0, min(je, ct) - jb);
                     } else {
-                        L = (je - jb) / sub;
+                        L = (je - jb) >> sub_sh;
                         jl0 = jb + part * L;
                     }
                     bool clamp = false;
@@ -330,6 +345,36 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                         if (__ballot(ion && cmin <= rcd2) != 0)
                             contact_pass<R, POT>(tile, jidx, jl0, L, xi, yi, zi, eps2, rcd2, ion, i, d,
                                                  &cacc[0][tid]);
+                    } else if (tailm) {
+                        const int Q = (je - jb) >> 2;
+                        const bool tail_lane = lane >= 48;
+#pragma unroll 1
+                        for (int pq = 0; pq < 3; ++pq) {
+                            const int src = 16 * pq + (lane & 15);
+                            const R tx = __shfl(xi, src, 64), ty = __shfl(yi, src, 64), tz = __shfl(zi, src, 64);
+                            if (tail_lane) {
+                                xi = tx;
+                                yi = ty;
+                                zi = tz;
+                                ax = ay = az = pot = (R)0;
+                            }
+                            const int j0 = tail_lane ? jb + 3 * Q : jb + pq * Q;
+                            if (eq)
+                                interact_lanes<R, POT, ZERO_EPS, false, true>(tile, j0, Q, xi, yi, zi, eps2, rce2,
+                                                                              ax, ay, az, pot, cmin);
+                            else
+                                interact_lanes<R, POT, ZERO_EPS, false, false>(tile, j0, Q, xi, yi, zi, eps2, rce2,
+                                                                               ax, ay, az, pot, cmin);
+                            const int tl = 48 + (lane & 15);
+                            const R sx = __shfl(ax, tl, 64), sy = __shfl(ay, tl, 64), sz = __shfl(az, tl, 64),
+                                    sp = __shfl(pot, tl, 64);
+                            if ((lane >> 4) == pq) {
+                                ax += sx;
+                                ay += sy;
+                                az += sz;
+                                pot += sp;
+                            }
+                        }
                     } else if (eq) {
                         tile_pass<R, POT, ZERO_EPS, false, true>(tile, sub, jl0, L, xi, yi, zi, eps2, rce2, ax, ay,
                                                                  az, pot, cmin);
@@ -346,7 +391,7 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                 const uint32_t cntt = min((uint32_t)TJ, npc - t0);
                 for (uint32_t e = tid; e < cntt; e += FT) {
                     const double4 m = d.nd_mom[d.pc_pool[pc0 + t0 + e]];
-                    tile[e] = mk4<R>((R)(m.x - cen.x), (R)(m.y - cen.y), (R)(m.z - cen.z), (R)(eqm ? m.w / m0 : m.w));
+                    tile[e] = mk4<R>((R)(m.x - cen.x), (R)(m.y - cen.y), (R)(m.z - cen.z), (R)(m.w * inv_m0));
                 }
                 compute_tile(cntt, false);
             }
