@@ -187,7 +187,10 @@ bh_status bh_set_params(bh_ctx *ctx, const bh_params *p);
 /* Sec. 4.2 (3a): root box, keys, sort and permutation, octree, node
  * moments, groups, for n_sys systems (sys[0..n_sys-1] host array of device
  * pointer sets).  Keeps a sorted FP64 copy of positions, velocities and
- * masses.  Invalidates lists. */
+ * masses.  Invalidates lists.  The sort is stable: particles with equal
+ * keys keep caller order.  Trees rebuilt inside bh_step / bh_step_continue
+ * sort from the context's previous sorted order instead, so there equal
+ * keys keep that order (the keys, tree, groups and lists are the same). */
 bh_status bh_build_tree(bh_ctx *ctx, const bh_system *sys, int32_t n_sys, void *stream);
 
 /* Sec. 4.2 (3d): walk the tree once per group and store its node list and
