@@ -381,11 +381,11 @@ bh_status ensure_nodes(bh_ctx *c, uint32_t cap) {
 
 bh_status ensure_walk(bh_ctx *c) {
     // at most 4 GiB of walk scratch: fewer walking waves when each needs more.
-    // The geometric walk keeps 24 waves per CU resident, the walk with the
-    // network in it (twice the registers) 16.
+    // The geometric walk keeps 32 waves per CU resident (8 workgroups at
+    // <= 64 VGPRs), the walk with the network in it (171 VGPRs) 16.
     const size_t per_wave = 2 * (size_t)c->walk_front + 2 * (size_t)c->walk_list;
     const size_t cap = ((size_t)1 << 30) / per_wave;
-    c->walk_waves = (uint32_t)(std::max<size_t>(std::min<size_t>(cap, (size_t)c->n_cu * 24), 64) & ~(size_t)3);
+    c->walk_waves = (uint32_t)(std::max<size_t>(std::min<size_t>(cap, (size_t)c->n_cu * 32), 64) & ~(size_t)3);
     c->walk_waves_net = (uint32_t)(std::max<size_t>(std::min<size_t>(cap, (size_t)c->n_cu * 16), 64) & ~(size_t)3);
     c->walk_waves_net = std::min(c->walk_waves_net, c->walk_waves);
     size_t words = (size_t)c->walk_waves * per_wave;
@@ -625,7 +625,7 @@ bh_status bh_create(bh_ctx **out, const bh_params *p) {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
         c->n_cu = ncu;
-    c->walk_waves = (uint32_t)c->n_cu * 24;
+    c->walk_waves = (uint32_t)c->n_cu * 32;
     c->walk_waves_net = (uint32_t)c->n_cu * 16;
     bool ok = hipHostMalloc((void **)&c->h_cnt, sizeof(DevCounters)) == hipSuccess &&
               hipEventCreateWithFlags(&c->tab_ev, hipEventDisableTiming) == hipSuccess &&

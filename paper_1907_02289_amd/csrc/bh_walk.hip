@@ -56,6 +56,54 @@ __device__ __forceinline__ bool accept_cell(int4 glo, int4 ghi, int Lx, int Ly, 
     return disjoint && ((double)s2 < th2 * (double)d2);
 }
 
+// The same test for the geometric walk, in 32-bit integers with the squared
+// distance summed in FP64: every doubled coordinate and gap is below 2^24
+// and every square below 2^47, so each step is exact and the decision is
+// the one above, bit for bit, in about half the instructions.
+__device__ __forceinline__ int gap2_i32(int C, int gl2, int gh2) {
+    return max(0, max(gl2 - C, C - gh2));
+}
+
+__device__ __forceinline__ bool accept_cell_geo(int4 glo, int4 ghi, int Lx, int Ly, int Lz, int level, double th2,
+                                                bool periodic) {
+    const int s = 1 << (BH_MAXLEVEL - level);
+    const int L[3] = {Lx, Ly, Lz};
+    const int gl[3] = {glo.x, glo.y, glo.z}, gh[3] = {ghi.x, ghi.y, ghi.z};
+    constexpr int TURN2 = 2 << BH_MAXLEVEL;
+    bool disjoint = false;
+    double d2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        disjoint |= (L[a] + s <= gl[a]) || (L[a] >= gh[a]);
+        const int C = 2 * L[a] + s;
+        int da = gap2_i32(C, 2 * gl[a], 2 * gh[a]);
+        if (a == 0 && periodic)
+            da = min(da, min(gap2_i32(C - TURN2, 2 * gl[a], 2 * gh[a]), gap2_i32(C + TURN2, 2 * gl[a], 2 * gh[a])));
+        d2 = fma((double)da, (double)da, d2);
+    }
+    const double s2 = (double)(4 * s) * (double)s;      // (2 s)^2
+    return disjoint && (s2 < th2 * d2);
+}
+
+// Number of set bits of m in the lanes below this one.
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Exclusive prefix sum over the lanes of a value in 0..15, and the wave
+// total, from four ballots (no cross-lane data movement).
+__device__ __forceinline__ uint32_t wave_excl_small(uint32_t v, uint32_t &tot) {
+    uint32_t pre = 0;
+    tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t b = __ballot((v >> k) & 1u);
+        pre += mbcnt(b) << k;
+        tot += (uint32_t)__popcll(b) << k;
+    }
+    return pre;
+}
+
 // Per-group constants of the learned rule.
 struct GroupCtx {
     int4 glo, ghi;
@@ -76,8 +124,8 @@ __device__ __forceinline__ bool decide(const DevState &d, const GroupCtx &gc, ui
     const int level = (int)((uint32_t)wr.x >> 24);
     const int Lx = wr.x & 0xffffff, Ly = wr.y & 0xffffff, Lz = wr.z;
     *cand = false;
-    if (GEO || d.walk_mode == WALK_GEOMETRIC)
-        return accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2, d.cyl_r > 0.0);
+    if (GEO) return accept_cell_geo(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2, d.cyl_r > 0.0);
+    if (d.walk_mode == WALK_GEOMETRIC) return accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2, d.cyl_r > 0.0);
     if (accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2_min)) return true;
     if (!accept_cell(gc.glo, gc.ghi, Lx, Ly, Lz, level, d.th2_max)) return false;
     const uint32_t cnt = d.nd_count[v];
@@ -94,7 +142,7 @@ __device__ __forceinline__ bool decide(const DevState &d, const GroupCtx &gc, ui
 }
 
 template <bool GEO>
-__global__ void __launch_bounds__(WALK_TPB, (GEO ? 6 : 1)) k_walk(DevState d) {
+__global__ void __launch_bounds__(WALK_TPB, (GEO ? 8 : 1)) k_walk(DevState d) {
     const uint32_t wave = (blockIdx.x * WALK_TPB + threadIdx.x) >> 6;
     if (wave >= d.walk_waves) return;
     const int lane = __lane_id();
@@ -138,6 +186,7 @@ __global__ void __launch_bounds__(WALK_TPB, (GEO ? 6 : 1)) k_walk(DevState d) {
         __threadfence_block();
         uint32_t ncur = 1, npc = 0, npp = 0;
         unsigned long long pp_particles = 0;
+        unsigned long long pp_lane = 0;          // geometric walk: this lane's share, summed once per group
         bool ovf = false;
         while (ncur > 0 && !ovf) {
             uint32_t nnext = 0;
@@ -162,18 +211,30 @@ __global__ void __launch_bounds__(WALK_TPB, (GEO ? 6 : 1)) k_walk(DevState d) {
 
                 const uint64_t mpc = __ballot(acc);
                 const uint64_t mpp = __ballot(is_pp);
-                const uint32_t opc = npc + (uint32_t)__popcll(mpc & lt);
-                const uint32_t opp = npp + (uint32_t)__popcll(mpp & lt);
-                if (acc && opc < P && !enumerate) pcb[opc] = v;
-                if (is_pp && opp < P && !enumerate) ppb[opp] = v;
-                unsigned long long cnt_pp = is_pp ? (unsigned long long)d.nd_count[v] : 0ull;
-                pp_particles += wave_sum(cnt_pp);
-                npc += (uint32_t)__popcll(mpc);
-                npp += (uint32_t)__popcll(mpp);
+                uint32_t o, tot;
+                if constexpr (GEO) {
+                    const uint32_t opc = npc + mbcnt(mpc);
+                    const uint32_t opp = npp + mbcnt(mpp);
+                    if (acc && opc < P) pcb[opc] = v;
+                    if (is_pp && opp < P) ppb[opp] = v;
+                    if (is_pp) pp_lane += d.nd_count[v];
+                    npc += (uint32_t)__popcll(mpc);
+                    npp += (uint32_t)__popcll(mpp);
+                    o = nnext + wave_excl_small(nopen, tot);
+                } else {
+                    const uint32_t opc = npc + (uint32_t)__popcll(mpc & lt);
+                    const uint32_t opp = npp + (uint32_t)__popcll(mpp & lt);
+                    if (acc && opc < P && !enumerate) pcb[opc] = v;
+                    if (is_pp && opp < P && !enumerate) ppb[opp] = v;
+                    unsigned long long cnt_pp = is_pp ? (unsigned long long)d.nd_count[v] : 0ull;
+                    pp_particles += wave_sum(cnt_pp);
+                    npc += (uint32_t)__popcll(mpc);
+                    npp += (uint32_t)__popcll(mpp);
 
-                const uint32_t incl = wave_incl_scan(nopen);
-                const uint32_t tot = __shfl(incl, 63, 64);
-                const uint32_t o = nnext + incl - nopen;
+                    const uint32_t incl = wave_incl_scan(nopen);
+                    tot = __shfl(incl, 63, 64);
+                    o = nnext + incl - nopen;
+                }
                 for (uint32_t c = 0; c < nopen; ++c)
                     if (o + c < F) nxt[o + c] = (uint32_t)wr.w + c;
                 nnext += tot;
@@ -202,6 +263,7 @@ __global__ void __launch_bounds__(WALK_TPB, (GEO ? 6 : 1)) k_walk(DevState d) {
             }
             continue;
         }
+        if constexpr (GEO) pp_particles = wave_sum(pp_lane);
         unsigned long long at_pc = 0, at_pp = 0;
         if (lane == 0) {
             at_pc = atomicAdd(&d.cnt->pc_used, (unsigned long long)npc);
