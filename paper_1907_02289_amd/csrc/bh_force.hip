@@ -49,6 +49,7 @@ namespace {
 constexpr int FT = 256;      // threads per workgroup (4 waves)
 constexpr int TJ = 512;      // sources per LDS tile (two per thread)
 constexpr int LC = FT;       // particle-list leaves per chunk (one per thread)
+constexpr int PIDX = 2048;   // particle ids of a leaf chunk listed in LDS (FP32 gravity-only kernels)
 
 template <typename R> struct V4;
 template <> struct V4<float> { using T = float4; };
@@ -220,6 +221,10 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
     __shared__ uint32_t wsum[4];
     __shared__ uint32_t jidx[COLL ? TJ : 1];            // sorted index of each particle-tile entry
     __shared__ double cacc[COLL ? 4 : 1][COLL ? FT : 1];  // per-thread FP64 contact sums
+    // the particle ids of a leaf chunk, in list order, so that staging a
+    // source is one LDS read instead of a search over the leaf offsets
+    constexpr bool LIST_IDS = sizeof(R) == 4 && !COLL;
+    __shared__ uint32_t pid[LIST_IDS ? PIDX : 1];
 
     const int tid = threadIdx.x;
     const int w = tid >> 6;
@@ -417,17 +422,27 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                 }
                 lbeg[tid] = lb;
                 lscan[tid] = off + inc - lc;
+                // a chunk of at most PIDX particles lists them all (each thread its
+                // leaf's); a larger one (a few big level-21 leaves) searches
+                const bool ids = LIST_IDS && tot <= (uint32_t)PIDX;
+                if (ids)
+                    for (uint32_t k = 0; k < lc; ++k) pid[off + inc - lc + k] = lb + k;
                 __syncthreads();
                 for (uint32_t p0 = 0; p0 < tot; p0 += TJ) {
                     const uint32_t cntt = min((uint32_t)TJ, tot - p0);
                     for (uint32_t e = tid; e < cntt; e += FT) {
                         const uint32_t f = p0 + e;
-                        uint32_t lo = 0, hi = nl - 1;          // last k with lscan[k] <= f
-                        while (lo < hi) {
-                            const uint32_t mid = (lo + hi + 1) >> 1;
-                            if (lscan[mid] <= f) lo = mid; else hi = mid - 1;
+                        uint32_t j;
+                        if (ids) {
+                            j = pid[f];
+                        } else {
+                            uint32_t lo = 0, hi = nl - 1;          // last k with lscan[k] <= f
+                            while (lo < hi) {
+                                const uint32_t mid = (lo + hi + 1) >> 1;
+                                if (lscan[mid] <= f) lo = mid; else hi = mid - 1;
+                            }
+                            j = lbeg[lo] + (f - lscan[lo]);
                         }
-                        const uint32_t j = lbeg[lo] + (f - lscan[lo]);
                         const double4 q = d.pos[j];
                         tile[e] = mk4<R>((R)(q.x - cen.x), (R)(q.y - cen.y), (R)(q.z - cen.z), (R)q.w);
                         if (COLL) jidx[e] = j;
