@@ -6,7 +6,8 @@
 // radix sort with 8-bit digits: per pass one histogram kernel, one scan of
 // the (digit, block) counts and one scatter kernel whose ranks come from
 // wave-level digit matching (eight ballots), so equal keys keep their input
-// order (stable).
+// order (stable).  The scatter first orders its tile by digit in LDS and then
+// writes each digit's run to consecutive addresses.
 #include "bh_internal.hpp"
 
 namespace {
@@ -16,8 +17,8 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 4;
 
 constexpr int RS_THREADS = 256;              // 4 waves
-constexpr int RS_WAVE_ITEMS = 16;            // rounds of 64 keys per wave
-constexpr int RS_TILE = RS_THREADS * RS_WAVE_ITEMS;   // 4096 keys per block
+constexpr int RS_WAVE_ITEMS = 8;             // rounds of 64 keys per wave
+constexpr int RS_TILE = RS_THREADS * RS_WAVE_ITEMS;   // 2048 keys per block
 
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, uint32_t *total) {
     // 256 threads = 4 waves; wsum: 4 words of LDS
@@ -136,6 +137,12 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *ke
                                                              const uint32_t *hist_scan, uint32_t nb,
                                                              const uint32_t *sys_off, int n_sys) {
     __shared__ uint32_t run[4][256];
+    __shared__ uint32_t loc[256];                // block-local start of each digit's run
+    __shared__ uint32_t gbase[256];              // global start of this block's run of each digit
+    __shared__ uint32_t wsum[4];
+    __shared__ uint64_t skey[RS_TILE];           // the tile in (digit, input) order
+    __shared__ uint32_t sval[RS_TILE];
+    __shared__ uint8_t sdig[RS_TILE];
     const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
 #pragma unroll
@@ -166,26 +173,40 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *ke
         digit[r] = d;
         rank[r] = old + (uint32_t)__popcll(peers & lt);
     }
-    // exclusive prefix over the four waves plus this block's global offset
+    // block-local start of each digit (scan over the digits), then of each
+    // wave's share of it; the block's global start of each digit
     {
-        uint32_t t = threadIdx.x;
-        uint32_t s = hist_scan[t * nb + blockIdx.x];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            uint32_t c = run[k][t];
-            run[k][t] = s;
-            s += c;
-        }
+        const uint32_t t = threadIdx.x;
+        const uint32_t c0 = run[0][t], c1 = run[1][t], c2 = run[2][t], c3 = run[3][t];
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(c0 + c1 + c2 + c3, wsum, &tot);
+        loc[t] = ex;
+        run[0][t] = ex;
+        run[1][t] = ex + c0;
+        run[2][t] = ex + c0 + c1;
+        run[3][t] = ex + c0 + c1 + c2;
+        gbase[t] = hist_scan[t * nb + blockIdx.x];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < RS_WAVE_ITEMS; ++r) {
-        uint32_t i = base + r * 64 + lane;
+        const uint32_t i = base + r * 64 + lane;
         if (i < n) {
-            uint32_t pos = run[w][digit[r]] + rank[r];
-            key_out[pos] = key_in[i];
-            val_out[pos] = val_in[i];
+            const uint32_t lp = run[w][digit[r]] + rank[r];
+            skey[lp] = key_in[i];
+            sval[lp] = val_in[i];
+            sdig[lp] = (uint8_t)digit[r];
         }
+    }
+    __syncthreads();
+    // consecutive threads write consecutive slots of each digit's run
+    const uint32_t t0 = blockIdx.x * RS_TILE;
+    const uint32_t cnt = n - t0 < (uint32_t)RS_TILE ? n - t0 : (uint32_t)RS_TILE;
+    for (uint32_t p = threadIdx.x; p < cnt; p += RS_THREADS) {
+        const uint32_t d = sdig[p];
+        const uint32_t pos = gbase[d] + (p - loc[d]);
+        key_out[pos] = skey[p];
+        val_out[pos] = sval[p];
     }
 }
 
