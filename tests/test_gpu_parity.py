@@ -110,6 +110,19 @@ def _coincident():
 CASES.append(("coincident40", _coincident, 0.5, 1e-3, 8, 32))
 
 
+def _coincident_big():
+    """2500 identical points in a 4000-particle ring: a level-21 leaf bigger than
+    the FP32 kernel's LDS list of a leaf chunk's particle ids (2048), so the chunks
+    that hold it locate their particles by search instead."""
+    s = inputs.ring(4000, 12)
+    for a in (s.x, s.y, s.z):
+        a[:2500] = a[0]
+    return s
+
+
+CASES.append(("coincident2500", _coincident_big, 0.5, 1e-3, 8, 64))
+
+
 def _mixed_masses():
     """Unequal masses: the FP32 kernel keeps the per-source mass in its loop
     (equal-mass systems take it out)."""
@@ -141,8 +154,12 @@ def test_structures_and_fp64_forces(torch_cuda, name, make, theta, eps, n_leaf, 
     ctx.close()
 
 
-@pytest.mark.parametrize("name,make,theta,eps,n_leaf,n_grp", CASES[:3] + CASES[-4:],
-                         ids=[c[0] for c in CASES[:3] + CASES[-4:]])
+FP32_CASES = [c for c in CASES if c[0] in ("ring4096", "ring3001_ragged", "plummer5000_g256", "ring20000_g300",
+                                           "coincident40", "coincident2500", "ring6000_mixed_masses",
+                                           "ring5000_eps0")]
+
+
+@pytest.mark.parametrize("name,make,theta,eps,n_leaf,n_grp", FP32_CASES, ids=[c[0] for c in FP32_CASES])
 def test_fp32_relative_forces(torch_cuda, name, make, theta, eps, n_leaf, n_grp):
     torch = torch_cuda
     _log(f"[gpu] fp32 {name}")
