@@ -318,7 +318,8 @@ def main():
     ap.add_argument("--reuse-study", action="store_true",
                     help="only the list-reuse study: matched-error theta and time per step for each rebuild interval")
     ap.add_argument("--learned", action="store_true",
-                    help="also train, tune and time the learned-criterion form (off by default: see the design notes)")
+                    help="also train, tune and time the learned-criterion form (off by default: its training-pair "
+                         "collection is kept off the GPU after an unexplained silent test run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: sharding the groups "

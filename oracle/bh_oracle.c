@@ -18,9 +18,8 @@
  *   - gravity term of the particle-particle interaction ......... Sec. 5.1, Eq. (2)
  *   - centre-of-mass (monopole) approximation for tree nodes .... Sec. 5.1
  * Where the paper is silent (key layout, tree split rule, group rule,
- * opening test) the functions implement the readings written out in the
- * design notes of this repository; each is repeated in the comment of the
- * function that implements it.
+ * opening test) the functions implement a stated reading of it; each reading
+ * is written out in the comment of the function that implements it.
  *
  * Precision: FP64 throughout, built with -O2 -ffp-contract=off and no
  * fast-math so that every expression rounds exactly as written.

@@ -181,7 +181,8 @@ def test_learned_rule_gain_at_matched_error(torch_cuda):
         set's mean label (tau).
     The trained network must need fewer interactions than the constant; the
     ratio to the geometric rule is reported (on this thin ring the geometric
-    box-distance rule stays ahead: see the design notes)."""
+    box-distance rule stays ahead: the per-node error keeps a scatter that the
+    four features do not resolve)."""
     torch = torch_cuda
     from paper_1907_02289_amd import bh
     eps = 1e-4
