@@ -388,19 +388,35 @@ def main():
                 e = rel_err_p99(ctx, dev0, sample, ref, n)
             else:
                 th, e = tune_theta(ctx, dev0, sample, ref, n)
-            # cost of one reuse cycle per step at this theta: walk / R + force
+            ctx.set_params(theta=th)
             ctx.make_lists()
-            ctx.forces(None)
-            st = ctx.stage_times()
-            cost = st["walk"] / p["rebuild_every"] + st["forces"]
-            log(f"[bench] {name} n_group={ng} {tc}: theta={th:.4f} p99={e[0]:.3e} cost {cost:.2f} ms")
+            inter = ctx.query()["interactions"]
+            ctx.close()
+            cost = None
+            if name == "tuned" and len(group_sizes) * len(tree_choices) > 1:
+                # cost at this theta where the timed region starts: the wall time
+                # per leapfrog step of one rebuild cycle after the same warm-up
+                cdev = {k: v.clone() for k, v in dev0.items()}
+                cc = bh.Context(theta=th, eps=w.eps, central_mass=w.central_mass, precision=p["precision"],
+                                n_group=ng, cyl_radius=coords[tc])
+                cc.step([cdev], w.dt, 0, R)
+                for _ in range(args.warmup):
+                    cc.step_continue(w.dt, R, R)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                cc.step_continue(w.dt, R, R)
+                torch.cuda.synchronize()
+                cost = (time.perf_counter() - t0) * 1e3 / R
+                cc.close()
+                del cdev
+            log(f"[bench] {name} n_group={ng} {tc}: theta={th:.4f} p99={e[0]:.3e}"
+                + (f" cost {cost:.2f} ms per step after warm-up" if cost is not None else ""))
             if name == "tuned":
                 autotune.append({"n_group": ng, "tree": tc, "theta": th, "p99": e[0],
-                                 "interactions_per_force_eval": ctx.query()["interactions"],
-                                 "ms_walk_per_step_plus_force": cost})
-            if best is None or cost < best[0]:
+                                 "interactions_per_force_eval": inter,
+                                 "ms_per_step_after_warmup": cost})
+            if best is None or (cost is not None and cost < best[0]):
                 best = (cost, ng, th, e, tc)
-            ctx.close()
             torch.cuda.empty_cache()
         p["n_group"], p["theta"], (p["p99"], p["p50"]), p["tree"] = best[1], best[2], best[3], best[4]
         p["cyl_radius"] = coords[best[4]]

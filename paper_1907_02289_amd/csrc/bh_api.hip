@@ -500,7 +500,7 @@ bh_status walk_until_fits(bh_ctx *c, hipStream_t s) {
     }
 }
 
-bh_status run_forces(bh_ctx *c, hipStream_t s, bool pot);
+bh_status run_forces(bh_ctx *c, hipStream_t s, bool pot, double kick_h = 0.0);
 
 bh_status order_lists(bh_ctx *c, hipStream_t s) {
     bhk::order_groups(c->d, c->n_groups, P<uint64_t>(c->gkey_a), P<uint32_t>(c->gval_a), P<uint64_t>(c->gkey_b),
@@ -536,7 +536,10 @@ bh_status make_lists(bh_ctx *c, hipStream_t s) {
 // 6 per CU by its register cap; FP64: 4 at its register use).
 int force_blocks(const bh_ctx *c) { return c->n_cu * (c->P.precision == BH_FP32_REL ? 6 : 4); }
 
-bh_status run_forces(bh_ctx *c, hipStream_t s, bool pot) {
+// kick_h != 0: the launch also applies the closing half kick v += kick_h a.
+// The kernels with the collision branch ignore it, so callers pass it only
+// when the branch is off.
+bh_status run_forces(bh_ctx *c, hipStream_t s, bool pot, double kick_h) {
     if (c->force_ev_used == c->force_ev.size()) {
         if (c->force_ev.size() >= 65536) {
             c->force_ev_used = 0;                    // drop the oldest window
@@ -550,7 +553,7 @@ bh_status run_forces(bh_ctx *c, hipStream_t s, bool pot) {
     auto &pr = c->force_ev[c->force_ev_used++];
     ev_begin(c, EV_FORCE, s);
     HIPCHK(c, hipEventRecord(pr.first, s));
-    bhk::forces(c->d, c->n_groups, c->P.precision == BH_FP32_REL, pot, force_blocks(c), s);
+    bhk::forces(c->d, c->n_groups, c->P.precision == BH_FP32_REL, pot, force_blocks(c), kick_h, s);
     HIPCHK(c, hipEventRecord(pr.second, s));
     ev_end(c, EV_FORCE, s);
     c->interactions_evaluated += (int64_t)c->interactions;
@@ -803,8 +806,11 @@ bh_status integrate(bh_ctx *c, double dt, int32_t n_steps, int32_t rebuild_every
             ev_end(c, EV_MOM, s);
         }
         refresh_state(c);
-        STCHK(run_forces(c, s, false));
-        bhk::kick(c->d, h, s);
+        // the closing kick rides in the force launch unless the collision
+        // branch is on (its dashpot reads other particles' velocities)
+        const bool fused = !(c->P.r_coll > 0.0);
+        STCHK(run_forces(c, s, false, fused ? h : 0.0));
+        if (!fused) bhk::kick(c->d, h, s);
     }
     bhk::scatter_state(c->d, s);
     HIPCHK(c, hipGetLastError());

@@ -211,7 +211,10 @@ struct ForceOcc {
 };
 
 template <typename R, bool POT, bool ZERO_EPS, bool COLL>
-__global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevState d, uint32_t ng) {
+// kick_h != 0: also apply the closing half kick v += kick_h a of a
+// leapfrog step to each particle, as a separate pass over v and a would (the
+// collision branch reads other particles' velocities, so it never fuses).
+__global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevState d, uint32_t ng, double kick_h) {
     using T4 = typename V4<R>::T;
     __shared__ T4 tile[TJ + 16];
     __shared__ uint32_t lbeg[LC];
@@ -505,6 +508,13 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                     gp += cp;
                 }
                 d.acc[i] = make_double4(gx, gy, gz, POT ? gp : 0.0);
+                if (!COLL && kick_h != 0.0) {
+                    double4 v = d.vel[i];
+                    v.x = v.x + kick_h * gx;
+                    v.y = v.y + kick_h * gy;
+                    v.z = v.z + kick_h * gz;
+                    d.vel[i] = v;
+                }
             }
             __syncthreads();
         }
@@ -516,16 +526,16 @@ __global__ void k_force_reset(DevState d) {
 }
 
 template <typename R, bool POT>
-void launch(const DevState &d, uint32_t ng, int blocks, hipStream_t s) {
+void launch(const DevState &d, uint32_t ng, int blocks, double kick_h, hipStream_t s) {
     if (d.rc > 0.0) {
         if (d.eps2 == 0.0)
-            k_force<R, POT, true, true><<<blocks, FT, 0, s>>>(d, ng);
+            k_force<R, POT, true, true><<<blocks, FT, 0, s>>>(d, ng, 0.0);
         else
-            k_force<R, POT, false, true><<<blocks, FT, 0, s>>>(d, ng);
+            k_force<R, POT, false, true><<<blocks, FT, 0, s>>>(d, ng, 0.0);
     } else if (d.eps2 == 0.0) {
-        k_force<R, POT, true, false><<<blocks, FT, 0, s>>>(d, ng);
+        k_force<R, POT, true, false><<<blocks, FT, 0, s>>>(d, ng, kick_h);
     } else {
-        k_force<R, POT, false, false><<<blocks, FT, 0, s>>>(d, ng);
+        k_force<R, POT, false, false><<<blocks, FT, 0, s>>>(d, ng, kick_h);
     }
 }
 
@@ -533,13 +543,15 @@ void launch(const DevState &d, uint32_t ng, int blocks, hipStream_t s) {
 
 namespace bhk {
 
-void forces(const DevState &d, uint32_t n_groups, bool fp32, bool pot, int blocks, hipStream_t s) {
+void forces(const DevState &d, uint32_t n_groups, bool fp32, bool pot, int blocks, double kick_h, hipStream_t s) {
     k_force_reset<<<1, 64, 0, s>>>(d);
     if (n_groups == 0) return;
     if (fp32) {
-        if (pot) launch<float, true>(d, n_groups, blocks, s); else launch<float, false>(d, n_groups, blocks, s);
+        if (pot) launch<float, true>(d, n_groups, blocks, kick_h, s);
+        else launch<float, false>(d, n_groups, blocks, kick_h, s);
     } else {
-        if (pot) launch<double, true>(d, n_groups, blocks, s); else launch<double, false>(d, n_groups, blocks, s);
+        if (pot) launch<double, true>(d, n_groups, blocks, kick_h, s);
+        else launch<double, false>(d, n_groups, blocks, kick_h, s);
     }
 }
 

@@ -215,7 +215,9 @@ void order_groups(const DevState &d, uint32_t n_groups, uint64_t *key_a, uint32_
                   uint32_t *val_b, hipStream_t s);
 
 // forces (bh_force.hip): blocks = persistent workgroups
-void forces(const DevState &d, uint32_t n_groups, bool fp32, bool pot, int blocks, hipStream_t s);
+// kick_h != 0 (no collision branch): the closing half kick v += kick_h a is
+// applied in the same launch; with the collision branch it is ignored.
+void forces(const DevState &d, uint32_t n_groups, bool fp32, bool pot, int blocks, double kick_h, hipStream_t s);
 
 // integration and caller-order output (bh_integrate.hip)
 struct AccPtr {
