@@ -196,3 +196,59 @@ def test_contacts_need_velocities(torch_cuda):
         ctx.set_params(kappa=-1.0)
     assert e.value.status == bh.BH_EINVAL
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_contacts_with_cylindrical_tree_and_two_systems(torch_cuda, precision):
+    """The collision branch, cylindrical tree coordinates and two systems in
+    one context together: each system's forces against the oracle for that
+    system alone, at the same bars as above."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log(f"[gpu] contacts + cylindrical + two systems, precision={precision}")
+    systems = [inputs.ring(9000, 39, v_disp=3e-3), inputs.ring(5000, 40, r_in=1.1, r_out=1.3, v_disp=3e-3)]
+    rc, eps, theta, n_grp, r_ref = 3e-3, 1e-4, 0.5, 64, 1.1
+    kappa, eta = contact_params(0.02, 0.5)
+    for s in systems:
+        assert _n_contacts(s, rc) > 20
+    ctx = bh.Context(theta=theta, eps=eps, n_group=n_grp, precision=precision, r_coll=rc, kappa=kappa, eta=eta,
+                     cyl_radius=r_ref)
+    dev = [bh.to_device(s) for s in systems]
+    ctx.build_tree(dev)
+    ctx.make_lists()
+    outs = [{k: torch.zeros(s.n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")} for s in systems]
+    ctx.forces(outs)
+    torch.cuda.synchronize()
+    for s, out in zip(systems, outs):
+        st = oracle.BHState(s.x, s.y, s.z, s.m, theta, 8, n_grp, cyl_r=r_ref)
+        ax, ay, az, _, mag = st.accel(s.x, s.y, s.z, s.m, eps, vel=(s.vx, s.vy, s.vz), contact=(rc, kappa, eta))
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        err = np.sqrt((g["ax"] - ax) ** 2 + (g["ay"] - ay) ** 2 + (g["az"] - az) ** 2)
+        if precision == 0:
+            assert np.all(err <= 1e-12 * mag), f"max err/mag {np.max(err / mag)}"
+        else:
+            rel = err / np.sqrt(ax ** 2 + ay ** 2 + az ** 2)
+            _log(f"    n={s.n}: fp32 rel err median {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e}")
+            assert np.median(rel) <= 1e-5
+    ctx.close()
+
+
+def test_step_fp64_contacts_cylindrical_matches_oracle(torch_cuda):
+    """KDK with contacts on a cylindrical tree, lists reused: within 1e-10 of
+    the oracle's trajectory."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log("[gpu] step fp64, contacts + cylindrical")
+    s = inputs.ring(4000, 38, central_mass=1.0, v_disp=3e-3)
+    theta, eps, dt, n, rc = 0.5, 1e-4, 1e-3, 7, 4e-3
+    kappa, eta = contact_params(0.02, 0.5)
+    ref = oracle.kdk(s.x, s.y, s.z, s.vx, s.vy, s.vz, s.m, dt, n, eps, central_mass=1.0, theta=theta, n_grp=64,
+                     rebuild_every=3, contact=(rc, kappa, eta), cyl_r=1.05)
+    ctx = bh.Context(theta=theta, eps=eps, n_group=64, precision=0, r_coll=rc, kappa=kappa, eta=eta,
+                     central_mass=1.0, cyl_radius=1.05)
+    dev = bh.to_device(s)
+    ctx.step([dev], dt, n, rebuild_every=3)
+    torch.cuda.synchronize()
+    for k, key in enumerate(("x", "y", "z", "vx", "vy", "vz")):
+        assert np.max(np.abs(dev[key].cpu().numpy() - ref[k])) < 1e-10, key
+    ctx.close()
