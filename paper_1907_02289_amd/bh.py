@@ -114,10 +114,16 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _ptr(t):
+def _ptr(t, n=None, what="array"):
+    """Device pointer of a contiguous CUDA FP64 tensor (of n elements when n is
+    given); anything else raises before the library could read past it."""
+    import torch
     if t is None:
         return None
-    assert t.is_cuda and t.dtype.is_floating_point and t.is_contiguous(), "need contiguous CUDA FP64 tensors"
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{what}: need a contiguous CUDA float64 tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{what}: {t.numel()} elements, expected {n}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -161,14 +167,16 @@ class Context:
     def _systems(systems):
         arr = (System * len(systems))()
         for k, s in enumerate(systems):
-            arr[k].n = s["x"].numel()
+            n = s["x"].numel()
+            arr[k].n = n
             for f in ("x", "y", "z", "vx", "vy", "vz", "m"):
-                setattr(arr[k], f, _ptr(s.get(f)))
+                setattr(arr[k], f, _ptr(s.get(f), n, f"system {k} {f}"))
         return arr
 
     def build_tree(self, systems):
         arr = self._systems(systems)
         self._check(self.L.bh_build_tree(self.h, arr, len(systems), _stream()))
+        self._sizes = [s["x"].numel() for s in systems]
 
     def make_lists(self):
         self._check(self.L.bh_make_lists(self.h, _stream()))
@@ -178,16 +186,20 @@ class Context:
         if outs is None:
             self._check(self.L.bh_forces(self.h, None, _stream()))
             return
+        sizes = getattr(self, "_sizes", None)
+        if sizes is not None and len(outs) != len(sizes):
+            raise ValueError(f"{len(outs)} output sets for {len(sizes)} systems")
         arr = (Accel * len(outs))()
         for k, o in enumerate(outs):
             for f in ("ax", "ay", "az", "pot"):
-                setattr(arr[k], f, _ptr(o.get(f)))
+                setattr(arr[k], f, _ptr(o.get(f), sizes[k] if sizes else None, f"output {k} {f}"))
         self._check(self.L.bh_forces(self.h, arr, _stream()))
 
     def step(self, systems, dt, n_steps, rebuild_every=1):
         arr = self._systems(systems)
         self._check(self.L.bh_step(self.h, arr, len(systems), float(dt), int(n_steps), int(rebuild_every),
                                    _stream()))
+        self._sizes = [s["x"].numel() for s in systems]
 
     def step_continue(self, dt, n_steps, rebuild_every=1):
         self._check(self.L.bh_step_continue(self.h, float(dt), int(n_steps), int(rebuild_every), _stream()))
@@ -196,10 +208,13 @@ class Context:
         """FP64 direct sum for the targets (int64 CUDA tensor) of one system;
         out: dict of ax, ay, az tensors of len(targets)."""
         import torch
-        assert targets.is_cuda and targets.dtype == torch.int64 and targets.is_contiguous()
+        if not (targets.is_cuda and targets.dtype == torch.int64 and targets.is_contiguous()):
+            raise TypeError("targets: need a contiguous CUDA int64 tensor")
         arr = self._systems([system])
-        self._check(self.L.bh_direct_sum(self.h, arr, C.c_void_p(targets.data_ptr()), targets.numel(),
-                                         _ptr(out["ax"]), _ptr(out["ay"]), _ptr(out["az"]), _stream()))
+        nt = targets.numel()
+        self._check(self.L.bh_direct_sum(self.h, arr, C.c_void_p(targets.data_ptr()), nt,
+                                         _ptr(out["ax"], nt, "ax"), _ptr(out["ay"], nt, "ay"),
+                                         _ptr(out["az"], nt, "az"), _stream()))
 
     def autotune(self, candidates=(64, 128, 256, 512), rebuild_every=4):
         arr = (C.c_int32 * len(candidates))(*candidates)
@@ -222,7 +237,8 @@ class Context:
         src = None
         if set is not None:
             src = np.ascontiguousarray(set, np.float32)
-            assert src.size == MLP_NPARAM
+            if src.size != MLP_NPARAM:
+                raise ValueError(f"mlp_weights: {src.size} values, expected {MLP_NPARAM}")
         self._check(self.L.bh_mlp_weights(self.h, w.ctypes.data_as(C.c_void_p),
                                           None if src is None else src.ctypes.data_as(C.c_void_p)))
         return w if set is None else src
@@ -244,7 +260,8 @@ class Context:
     def mlp_predict(self, X):
         import torch
         X = X.contiguous()
-        assert X.is_cuda and X.dtype == torch.float32 and X.shape[-1] == 4
+        if not (X.is_cuda and X.dtype == torch.float32 and X.dim() == 2 and X.shape[1] == 4):
+            raise TypeError("mlp_predict: need a CUDA float32 tensor of shape (n, 4)")
         out = torch.zeros(X.shape[0], dtype=torch.float32, device=X.device)
         self._check(self.L.bh_mlp_predict(self.h, C.c_void_p(X.data_ptr()), X.shape[0],
                                           C.c_void_p(out.data_ptr()), _stream()))
@@ -253,6 +270,9 @@ class Context:
     def mlp_gradient(self, X, Y):
         import torch
         X, Y = X.contiguous(), Y.contiguous()
+        if not (X.is_cuda and Y.is_cuda and X.dtype == torch.float32 and Y.dtype == torch.float32
+                and X.dim() == 2 and X.shape[1] == 4 and Y.numel() == X.shape[0]):
+            raise TypeError("mlp_gradient: need CUDA float32 X (B x 4) and Y (B)")
         grad = torch.zeros(1249, dtype=torch.float32, device=X.device)
         loss = torch.zeros(1, dtype=torch.float32, device=X.device)
         self._check(self.L.bh_mlp_gradient(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),

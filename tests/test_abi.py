@@ -42,3 +42,14 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_binding_rejects_tensors_the_library_cannot_take():
+    """The binding hands the library only contiguous CUDA float64 tensors of
+    the expected length; anything else raises before a pointer is passed."""
+    import torch
+    from paper_1907_02289_amd import bh
+    assert bh._ptr(None) is None
+    for t in (torch.zeros(4, dtype=torch.float64), torch.zeros(4, dtype=torch.float32), [0.0] * 4):
+        with pytest.raises(TypeError):
+            bh._ptr(t, 4, "x")
