@@ -23,11 +23,11 @@
 // first and the tail is made of short ones.  All four waves of a workgroup
 // share one LDS tile of sources (the paper's cores sharing a cache on one
 // list).  The waves take 64-particle chunks of the group, the waves left
-// over splitting the source range; a chunk of at most 32 (16) particles -- a
-// small group, or the last chunk of a larger one -- spreads its wave over 2
-// (4) sub-slices of 32 (16) lanes, each on its own part of the source range
-// (the tile padded with massless sources), so partial chunks do not leave
-// most of their lanes idle.
+// over splitting the source range; a chunk of at most 32 (16, 8) particles --
+// a small group, or the last chunk of a larger one -- spreads its wave over 2
+// (4, 8) sub-slices of 32 (16, 8) lanes, each on its own part of the source
+// range (the tile padded with massless sources), so partial chunks do not
+// leave most of their lanes idle.
 // Partial sums are added in a fixed order, so results do not depend on
 // timing.
 //
@@ -264,8 +264,8 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
             const uint32_t nb = min((uint32_t)FT, gi.count - ib);
             // Waves take 64-particle chunks of the block (n_ic of them), the
             // waves left over splitting the source range (split ways).  A chunk
-            // of at most 32 (16) particles -- a small group, or the last chunk
-            // of a larger one -- spreads its wave over 2 (4) sub-slices of its
+            // of at most 32 (16, 8) particles -- a small group, or the last chunk
+            // of a larger one -- spreads its wave over 2 (4, 8) sub-slices of its
             // source range: cw lanes per particle, sub = 64 / cw parts.
             // split, sub and cw are powers of two: their divisions are shifts
             const int n_ic = (int)((nb + 63) >> 6);
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
             const int jslice = w / n_ic;
             const bool wave_on = jslice < split;
             const int cnt_w = min(64, (int)nb - 64 * ichunk);
-            const int cw_sh = cnt_w <= 16 ? 4 : (cnt_w <= 32 ? 5 : 6);
+            const int cw_sh = cnt_w <= 8 ? 3 : (cnt_w <= 16 ? 4 : (cnt_w <= 32 ? 5 : 6));
             const int cw = 1 << cw_sh;
             const int sub_sh = 6 - cw_sh;
             const int sub = 1 << sub_sh;                             // 64 / cw
@@ -311,21 +311,21 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
 
             // The staged tile holds cntt sources.  With a sub-sliced chunk in the
             // block the tile is padded with massless far sources to a multiple of
-            // 4 split entries and cut at multiples of 4, so that every part has
+            // 8 split entries and cut at multiples of 8, so that every part has
             // the same length; full chunks still stop at the last real entry.
             // particles: whether the tile holds particle sources (the only ones
             // the collision branch applies to).
             auto compute_tile = [&](uint32_t cntt, bool particles) {
                 const int ct = (int)cntt;
-                const int cntp = any_sub ? ((ct + (4 << split_sh) - 1) >> (2 + split_sh)) << (2 + split_sh) : ct;
+                const int cntp = any_sub ? ((ct + (8 << split_sh) - 1) >> (3 + split_sh)) << (3 + split_sh) : ct;
                 for (int t = ct + tid; t < cntp; t += FT) tile[t] = mk4<R>((R)1e18, (R)1e18, (R)1e18, (R)0);
                 __syncthreads();
                 if (wave_on) {
                     int jb, je;
                     if (any_sub) {
-                        const int q = cntp >> 2;
-                        jb = 4 * ((q * jslice) >> split_sh);
-                        je = 4 * ((q * (jslice + 1)) >> split_sh);
+                        const int q = cntp >> 3;
+                        jb = 8 * ((q * jslice) >> split_sh);
+                        je = 8 * ((q * (jslice + 1)) >> split_sh);
                     } else {
                         jb = (ct * jslice) >> split_sh;
                         je = (ct * (jslice + 1)) >> split_sh;
@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
             // ---- add the j-slices in a fixed order and write FP64 results
             if (cw < 64) {
 #pragma unroll
-                for (int off = 32; off >= 16; off >>= 1) {
+                for (int off = 32; off >= 8; off >>= 1) {
                     if (off < cw) break;
                     ax += __shfl_xor(ax, off, 64);
                     ay += __shfl_xor(ay, off, 64);
