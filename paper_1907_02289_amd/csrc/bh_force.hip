@@ -275,20 +275,29 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
             const int jslice = w / n_ic;
             const bool wave_on = jslice < split;
             const int cnt_w = min(64, (int)nb - 64 * ichunk);
-            const int cw_sh = cnt_w <= 8 ? 3 : (cnt_w <= 16 ? 4 : (cnt_w <= 32 ? 5 : 6));
+            // Slices of 8 particles in the chunk.  With 3, 5 or 7 of them the
+            // chunk runs in eighths mode: lanes 0..8S-1 hold the particles and
+            // take the first S eighths of the wave's source range; each of the
+            // 8-S other groups of 8 lanes takes one of the last eighths for the
+            // S slices in turn and hands each slice's partial sums to the lanes
+            // that own them.  Every lane then runs S/8 of the range.
+            const int s8 = (cnt_w + 7) >> 3;
+            const bool e8 = TAIL && (s8 == 3 || s8 == 5 || s8 == 7);
+            const int cw_sh = e8 ? 6 : (cnt_w <= 8 ? 3 : (cnt_w <= 16 ? 4 : (cnt_w <= 32 ? 5 : 6)));
             const int cw = 1 << cw_sh;
             const int sub_sh = 6 - cw_sh;
             const int sub = 1 << sub_sh;                             // 64 / cw
             const int part = lane >> cw_sh;
-            // A chunk of 33 to 48 particles runs in tail mode: lanes 0..47 hold
+            // A chunk of 41 to 48 particles runs in tail mode: lanes 0..47 hold
             // the particles and take the first three quarters of the wave's
             // source range; lanes 48..63 take the last quarter for the three
             // 16-particle slices in turn and hand each slice's partial sums to
             // the lanes that own them.  Every lane then runs 3/4 of the range
             // instead of a full wave running all of it.
-            const bool tailm = TAIL && cnt_w > 32 && cnt_w <= 48;
+            const bool tailm = TAIL && cnt_w > 40 && cnt_w <= 48;
             const int last_cnt = (int)nb - 64 * (n_ic - 1);
-            const bool any_sub = last_cnt <= (TAIL ? 48 : 32);       // the block's last chunk is sub-sliced or tailed
+            // the block's last chunk is sub-sliced, tailed or in eighths
+            const bool any_sub = last_cnt <= (TAIL ? 56 : 32);
             const uint32_t il = 64 * ichunk + (lane & (cw - 1));
             const bool ion = wave_on && il < nb;
             const uint32_t i = gi.begin + ib + il;
@@ -353,6 +362,40 @@ __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevSt
                         if (__ballot(ion && cmin <= rcd2) != 0)
                             contact_pass<R, POT>(tile, jidx, jl0, L, xi, yi, zi, eps2, rcd2, ion, i, d,
                                                  &cacc[0][tid]);
+                    } else if (e8) {
+                        const int Q = (je - jb) >> 3;
+                        const int lg = lane >> 3;
+                        const bool tail_lane = lg >= s8;
+#pragma unroll 1
+                        for (int pq = 0; pq < s8; ++pq) {
+                            const int src = 8 * pq + (lane & 7);
+                            const R tx = __shfl(xi, src, 64), ty = __shfl(yi, src, 64), tz = __shfl(zi, src, 64);
+                            if (tail_lane) {
+                                xi = tx;
+                                yi = ty;
+                                zi = tz;
+                                ax = ay = az = pot = (R)0;
+                            }
+                            // owners: eighth pq of their own slice; others: their own eighth
+                            const int j0 = jb + (tail_lane ? lg : pq) * Q;
+                            if (eq)
+                                interact_lanes<R, POT, ZERO_EPS, false, true>(tile, j0, Q, xi, yi, zi, eps2, rce2,
+                                                                              ax, ay, az, pot, cmin);
+                            else
+                                interact_lanes<R, POT, ZERO_EPS, false, false>(tile, j0, Q, xi, yi, zi, eps2, rce2,
+                                                                               ax, ay, az, pot, cmin);
+                            for (int t = s8; t < 8; ++t) {
+                                const int tl = 8 * t + (lane & 7);
+                                const R sx = __shfl(ax, tl, 64), sy = __shfl(ay, tl, 64), sz = __shfl(az, tl, 64),
+                                        sp = __shfl(pot, tl, 64);
+                                if (lg == pq) {
+                                    ax += sx;
+                                    ay += sy;
+                                    az += sz;
+                                    pot += sp;
+                                }
+                            }
+                        }
                     } else if (tailm) {
                         const int Q = (je - jb) >> 2;
                         const bool tail_lane = lane >= 48;
