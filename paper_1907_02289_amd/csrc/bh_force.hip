@@ -23,11 +23,13 @@
 // first and the tail is made of short ones.  All four waves of a workgroup
 // share one LDS tile of sources (the paper's cores sharing a cache on one
 // list).  The waves take 64-particle chunks of the group, the waves left
-// over splitting the source range; a chunk of at most 32 (16, 8) particles --
-// a small group, or the last chunk of a larger one -- spreads its wave over 2
-// (4, 8) sub-slices of 32 (16, 8) lanes, each on its own part of the source
-// range (the tile padded with massless sources), so partial chunks do not
-// leave most of their lanes idle.
+// over splitting the source range.  A partial chunk -- a small group, or the
+// last chunk of a larger one -- keeps most of its lanes busy: at most 8, 16 or
+// 25..32 particles spread the wave over 8, 4 or 2 sub-slices of the source
+// range; 17..24, 33..40 and 49..56 particles (3, 5, 7 slices of 8) run in
+// eighths mode and 41..48 in tail mode, where the lanes without particles
+// take the last parts of the range for the particles' slices in turn (the
+// tile is padded with massless sources so that every part has one length).
 // Partial sums are added in a fixed order, so results do not depend on
 // timing.
 //
