@@ -15,8 +15,12 @@
 // m0, the sums being scaled by G m0 at the end: one multiply fewer per pair.
 //
 // Sources are staged 512 at a time in LDS as group-relative float4 (x, y,
-// z, m); particle-list leaves are read 256 at a time and their particles
-// located in the tile by a prefix sum over the leaf sizes.
+// z, m); particle-list leaves are read 256 at a time, a prefix sum over their
+// sizes places their particles in the tiles, and the FP32 gravity-only
+// kernels list the chunk's particle ids in LDS once so that staging a source
+// is one LDS read (a chunk of more than 2048 particles, possible only with
+// big level-21 leaves, searches the leaf offsets instead).  Inside a leapfrog
+// step these kernels also apply the closing half kick to each particle.
 //
 // Scheduling (Sec. 4.6): a persistent grid takes groups from an atomic
 // queue in order of decreasing interaction count, so the longest lists start
@@ -43,7 +47,10 @@
 // dx*dx + dy*dy + dz*dz <= rc^2 and the spring and dashpot terms are taken
 // in FP64 from the absolute positions and velocities, and summed in FP64
 // apart from the gravity sums.  Particle tiles thus run the 13-instruction
-// body plus a max and a min; node tiles run the plain loop.
+// body plus a max and a min; node tiles run the plain loop.  These kernels
+// use the sub-slice modes only (no tail or eighths mode, no id list, no
+// fused kick: their LDS and registers are at the six-workgroup limit, and the
+// dashpot reads other particles' velocities).
 #include "bh_internal.hpp"
 
 namespace {
