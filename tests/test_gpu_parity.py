@@ -489,3 +489,45 @@ def test_autotune_picks_a_candidate_and_keeps_exact_lists(torch_cuda):
     np.testing.assert_array_equal(pc, st.pc)
     np.testing.assert_array_equal(pp, st.pp)
     ctx.close()
+
+
+def test_fp32_every_partial_chunk_size(torch_cuda):
+    """One system per size 1..300, each a single group (n_group 512): every
+    partial-chunk form of the FP32 kernel (8-, 16- and 32-lane sub-slices,
+    eighths mode, tail mode, full chunks, and a second pass for groups above
+    256) meets the FP32 bar.  Inside one group no node is accepted, so each
+    system's answer is its direct sum, from the oracle."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log("[gpu] fp32, systems of 1..300 particles")
+    rng = np.random.default_rng(31)
+    systems = []
+    for c in range(1, 301):
+        x, y, z = (rng.normal(0.0, 1.0, c) for _ in range(3))
+        m = np.full(c, 1.0 / c) if c % 2 else rng.uniform(0.5, 1.5, c) / c
+        systems.append((x, y, z, m))
+    dev = []
+    for x, y, z, m in systems:
+        t = {k: torch.as_tensor(v, device="cuda") for k, v in (("x", x), ("y", y), ("z", z), ("m", m))}
+        dev.append(t)
+    ctx = bh.Context(theta=0.5, eps=1e-3, n_group=512, precision=bh.FP32_REL)
+    ctx.build_tree(dev)
+    ctx.make_lists()
+    assert ctx.query()["n_groups"] == len(systems)
+    outs = [{k: torch.zeros(s[0].size, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+            for s in systems]
+    ctx.forces(outs)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for (x, y, z, m), out in zip(systems, outs):
+        if x.size == 1:
+            assert all(float(out[k].abs().max()) == 0.0 for k in ("ax", "ay", "az"))
+            continue
+        ax, ay, az, _ = oracle.direct(x, y, z, m, 1e-3)
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        rel = np.sqrt((g["ax"] - ax) ** 2 + (g["ay"] - ay) ** 2 + (g["az"] - az) ** 2) / \
+            np.sqrt(ax ** 2 + ay ** 2 + az ** 2)
+        assert np.median(rel) <= 1e-5, (x.size, np.median(rel))
+        worst = max(worst, float(rel.max()))
+    _log(f"    largest fp32 relative error over all sizes {worst:.2e}")
+    ctx.close()
