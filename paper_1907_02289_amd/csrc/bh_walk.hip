@@ -23,6 +23,7 @@
 namespace {
 
 constexpr int WALK_TPB = 256;
+constexpr int WALK_LFRONT = 512;    // geometric walk: frontier entries kept in LDS per wave and buffer
 
 // doubled distance from the doubled coordinate C to [gl, gh]
 __device__ __forceinline__ int64_t gap2(int64_t C, int64_t gl, int64_t gh) {
@@ -153,6 +154,14 @@ __global__ void __launch_bounds__(WALK_TPB, (GEO ? 8 : 1)) k_walk(DevState d) {
     uint32_t *pcb = fb + F;
     uint32_t *ppb = pcb + P;
     const uint32_t ng = d.cnt->n_groups;
+    // geometric walk: the first WALK_LFRONT entries of each frontier live in
+    // LDS, the rest at the same index in the wave's global scratch
+    uint32_t *la = nullptr, *lb = nullptr;
+    if constexpr (GEO) {
+        __shared__ uint32_t lfront[WALK_TPB / 64][2][WALK_LFRONT];
+        la = lfront[threadIdx.x >> 6][0];
+        lb = lfront[threadIdx.x >> 6][1];
+    }
 
     for (;;) {
         uint32_t g = 0;
@@ -182,7 +191,11 @@ __global__ void __launch_bounds__(WALK_TPB, (GEO ? 8 : 1)) k_walk(DevState d) {
             continue;
         }
         uint32_t *cur = fa, *nxt = fb;
-        if (lane == 0) cur[0] = gi.sys;          // root of the group's system
+        uint32_t *lcur = la, *lnxt = lb;
+        if (lane == 0) {
+            if constexpr (GEO) lcur[0] = gi.sys;  // root of the group's system
+            else cur[0] = gi.sys;
+        }
         __threadfence_block();
         uint32_t ncur = 1, npc = 0, npp = 0;
         unsigned long long pp_particles = 0;
@@ -193,7 +206,9 @@ __global__ void __launch_bounds__(WALK_TPB, (GEO ? 8 : 1)) k_walk(DevState d) {
             for (uint32_t base = 0; base < ncur; base += 64) {
                 const uint32_t k = base + lane;
                 const bool valid = k < ncur;
-                const uint32_t v = valid ? cur[k] : 0u;
+                uint32_t v;
+                if constexpr (GEO) v = valid ? (k < (uint32_t)WALK_LFRONT ? lcur[k] : cur[k]) : 0u;
+                else v = valid ? cur[k] : 0u;
                 int4 wr = valid ? d.nd_walk[v] : make_int4(0, 0, 0, 0);
                 const int nch = (int)((uint32_t)wr.y >> 24);
                 bool is_cand = false;
@@ -236,12 +251,19 @@ __global__ void __launch_bounds__(WALK_TPB, (GEO ? 8 : 1)) k_walk(DevState d) {
                     o = nnext + incl - nopen;
                 }
                 for (uint32_t c = 0; c < nopen; ++c)
-                    if (o + c < F) nxt[o + c] = (uint32_t)wr.w + c;
+                    if constexpr (GEO) {
+                        const uint32_t q = o + c;
+                        if (q < (uint32_t)WALK_LFRONT) lnxt[q] = (uint32_t)wr.w + c;
+                        else if (q < F) nxt[q] = (uint32_t)wr.w + c;
+                    } else if (o + c < F) {
+                        nxt[o + c] = (uint32_t)wr.w + c;
+                    }
                 nnext += tot;
             }
             if (nnext > F || (!enumerate && (npc > P || npp > P))) ovf = true;
             __threadfence_block();
             uint32_t *t = cur; cur = nxt; nxt = t;
+            if constexpr (GEO) { t = lcur; lcur = lnxt; lnxt = t; }
             ncur = nnext;
         }
         if (ovf) {
