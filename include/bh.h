@@ -85,7 +85,7 @@ typedef struct {
     int32_t n_group;       /* largest group; <= 0 lets the autotuner choose */
     int32_t precision;     /* bh_precision */
     int32_t criterion;     /* bh_criterion */
-    double theta_min, theta_max, tau;   /* learned rule only */
+    double theta_min, theta_max, tau;   /* learned rule only: finite, >= 0 */
     int32_t flags;         /* BH_FLAG_* bits */
     /* Collision branch of Eq. (2) (Sec. 5.1), on when r_coll > 0.  For a
      * particle pair with r = |r_ij| <= r_coll (decided in FP64 on the
@@ -166,7 +166,8 @@ typedef enum {
     BH_EXPORT_LISTS = 5,      /* CSR: int64 pc_off[n_groups+1], int64 pp_off[n_groups+1],
                                  uint32 pc[n_pc], uint32 pp[n_pp], packed in that order,
                                  each list in ascending node id */
-    BH_EXPORT_ACC_SORTED = 6, /* double[n_particles][4]: ax, ay, az, pot in sorted order */
+    BH_EXPORT_ACC_SORTED = 6, /* double[n_particles][4]: ax, ay, az, pot in sorted order, from the
+                                 last force evaluation (BH_ESTATE before one) */
     BH_EXPORT_SORTED_POS = 7, /* double[n_particles][4]: x, y, z, m in sorted order */
     BH_EXPORT_QUAD = 8,       /* double[n_nodes][6]: second moment about the com (xx,xy,xz,yy,yz,zz);
                                  learned rule only */
@@ -180,8 +181,11 @@ typedef enum {
 bh_status bh_create(bh_ctx **out, const bh_params *p);
 /* Free the context and all its device memory (synchronises the device). */
 bh_status bh_destroy(bh_ctx *ctx);
-/* Replace the parameters; invalidates lists.  theta and n_group changes need
- * bh_make_lists (and, for n_group, bh_build_tree) again. */
+/* Replace the parameters; invalidates lists, so bh_make_lists is needed
+ * again.  A change of n_group, n_leaf, criterion or cyl_radius also
+ * invalidates the tree (bh_make_lists then returns BH_ESTATE until
+ * bh_build_tree).  BH_EINVAL for out-of-range parameters (the context keeps
+ * the old ones). */
 bh_status bh_set_params(bh_ctx *ctx, const bh_params *p);
 
 /* Sec. 4.2 (3a): root box, keys, sort and permutation, octree, node
@@ -298,13 +302,14 @@ bh_status bh_mlp_weights(bh_ctx *ctx, float *get, const float *set);
 bh_status bh_mlp_dataset(bh_ctx *ctx, int64_t *n, uint32_t *pairs, float *x, float *y);
 bh_status bh_mlp_clear(bh_ctx *ctx);
 
-/* Network output for n feature rows (device float[n][4] -> device float[n]). */
+/* Network output for n feature rows (device float[n][4] -> device float[n]).
+ * BH_ESTATE until weights are set (bh_mlp_weights) or trained. */
 bh_status bh_mlp_predict(bh_ctx *ctx, const float *x, int64_t n, float *out, void *stream);
 
 /* Gradient of the mean squared error (on the normalised label) of a batch
  * (device x float[B][4], y float[B], B <= 65536) with respect to the first
  * 1249 weights, and the loss, into device memory; the weights are not
- * changed. */
+ * changed.  BH_ESTATE until weights are set or trained. */
 bh_status bh_mlp_gradient(bh_ctx *ctx, const float *x, const float *y, int32_t B, float *grad, float *loss,
                           void *stream);
 

@@ -159,9 +159,14 @@ class Context:
             pass
 
     def set_params(self, **kw):
+        old = {k: getattr(self.params, k) for k in kw}
         for k, v in kw.items():
             setattr(self.params, k, v)
-        self._check(self.L.bh_set_params(self.h, C.byref(self.params)))
+        st = self.L.bh_set_params(self.h, C.byref(self.params))
+        if st != BH_OK:
+            for k, v in old.items():          # the library kept its parameters: so does the mirror
+                setattr(self.params, k, v)
+        self._check(st)
 
     @staticmethod
     def _systems(systems):

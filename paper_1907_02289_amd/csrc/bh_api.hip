@@ -254,6 +254,9 @@ bh_status check_params(const bh_params *p) {
     if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return BH_EINVAL;
     if (!(p->cyl_radius >= 0.0) || !std::isfinite(p->cyl_radius)) return BH_EINVAL;
     if (p->cyl_radius > 0.0 && p->criterion == BH_OPEN_LEARNED) return BH_EINVAL;
+    if (p->criterion == BH_OPEN_LEARNED)
+        for (double v : {p->theta_min, p->theta_max, p->tau})
+            if (!(v >= 0.0) || !std::isfinite(v)) return BH_EINVAL;
     return BH_OK;
 }
 
@@ -686,7 +689,11 @@ bh_status bh_set_params(bh_ctx *c, const bh_params *p) {
     if (!c) return BH_EINVAL;
     if (check_params(p) != BH_OK) return fail(c, BH_EINVAL, "invalid parameters");
     int ng = p->n_group > 0 ? p->n_group : 64;
-    if (ng != c->n_grp_used || p->n_leaf != c->P.n_leaf || p->criterion != c->P.criterion) c->tree_valid = false;
+    // the tree depends on the leaf and group sizes, on the criterion (second
+    // moments) and on the coordinates it is built in
+    if (ng != c->n_grp_used || p->n_leaf != c->P.n_leaf || p->criterion != c->P.criterion ||
+        p->cyl_radius != c->P.cyl_radius)
+        c->tree_valid = false;
     c->P = *p;
     c->n_grp_used = ng;
     c->lists_valid = false;
@@ -1108,6 +1115,7 @@ bh_status bh_mlp_clear(bh_ctx *c) {
 
 bh_status bh_mlp_predict(bh_ctx *c, const float *x, int64_t n, float *out, void *stream) {
     if (!c || (n > 0 && (!x || !out)) || n < 0) return BH_EINVAL;
+    if (!c->mlp_ready) return fail(c, BH_ESTATE, "bh_mlp_predict: no weights (bh_mlp_train or bh_mlp_weights)");
     bhk::mlp_eval(P<float>(c->mlp_w), reinterpret_cast<const float4 *>(x), (uint64_t)n, out, (hipStream_t)stream);
     HIPCHK(c, hipGetLastError());
     return BH_OK;
@@ -1116,6 +1124,7 @@ bh_status bh_mlp_predict(bh_ctx *c, const float *x, int64_t n, float *out, void 
 bh_status bh_mlp_gradient(bh_ctx *c, const float *x, const float *y, int32_t B, float *grad, float *loss,
                           void *stream) {
     if (!c || !x || !y || !grad || B < 1 || B > 65536) return BH_EINVAL;
+    if (!c->mlp_ready) return fail(c, BH_ESTATE, "bh_mlp_gradient: no weights (bh_mlp_train or bh_mlp_weights)");
     hipStream_t s = (hipStream_t)stream;
     STCHK(ensure_mlp_train_buffers(c, (uint32_t)B, (uint64_t)B));
     bhk::perm_keys(P<uint64_t>(c->pk_a), P<uint32_t>(c->pv_a), (uint64_t)B, 0, s);   // identity order
@@ -1227,9 +1236,11 @@ bh_status bh_export(bh_ctx *c, int32_t what, void *dst, void *stream) {
         return BH_OK;
     }
     case BH_EXPORT_ACC_SORTED:
+        if (!c->state_valid) return fail(c, BH_ESTATE, "no accelerations");
         HIPCHK(c, hipMemcpy(dst, c->acc.p, n * sizeof(double4), hipMemcpyDeviceToHost));
         return BH_OK;
     case BH_EXPORT_SORTED_POS:
+        if (!c->n) return fail(c, BH_ESTATE, "no particles");
         HIPCHK(c, hipMemcpy(dst, c->pos.p, n * sizeof(double4), hipMemcpyDeviceToHost));
         return BH_OK;
     case BH_EXPORT_QUAD:

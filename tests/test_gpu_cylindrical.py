@@ -115,3 +115,25 @@ def test_cylindrical_rejections(torch_cuda):
     with pytest.raises(bh.BHError) as e:
         bh.Context(theta=0.5, eps=1e-3, cyl_radius=1.0, criterion=bh.LEARNED)
     assert e.value.status == bh.BH_EINVAL
+
+
+def test_changing_tree_coordinates_needs_a_new_tree(torch_cuda):
+    """The tree is built in the coordinates cyl_radius selects, so changing it
+    through bh_set_params invalidates the tree: bh_make_lists is BH_ESTATE
+    until bh_build_tree, and the rebuilt tree and lists are then the oracle's
+    cylindrical ones, bit-exact."""
+    from paper_1907_02289_amd import bh
+    _log("[gpu] cyl_radius change after a Cartesian build")
+    s = inputs.ring(6000, 45)
+    ctx = bh.Context(theta=0.5, eps=1e-3, n_group=64)
+    ctx.build_tree([bh.to_device(s)])
+    ctx.make_lists()
+    ctx.set_params(cyl_radius=1.05)
+    with pytest.raises(bh.BHError) as e:
+        ctx.make_lists()
+    assert e.value.status == bh.BH_ESTATE
+    ctx.build_tree([bh.to_device(s)])
+    ctx.make_lists()
+    st = oracle.BHState(s.x, s.y, s.z, s.m, 0.5, 8, 64, cyl_r=1.05)
+    _compare_structures(ctx, st, s.n)
+    ctx.close()

@@ -124,3 +124,30 @@ def test_learned_walk_with_fixed_weights(torch_cuda):
     assert got[1].size != lo[1].size and got[1].size != hi[1].size
     _log(f"    node-list entries: theta_max {hi[1].size}, learned {got[1].size}, theta_min {lo[1].size}")
     ctx.close()
+
+
+def test_parameters_and_calls_without_weights(torch_cuda):
+    """The network calls need weights: inference and gradient are BH_ESTATE
+    until weights are set, then run.  Out-of-range band parameters of the
+    learned rule are BH_EINVAL, and the context (and the binding's copy)
+    keep the previous ones."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log("[gpu] learned network: calls without weights, parameter checks")
+    ctx = bh.Context(theta=0.5, eps=1e-3, n_group=64, criterion=bh.LEARNED)
+    X, Y = _synthetic(100, 9)
+    Xd, Yd = torch.as_tensor(X, device="cuda"), torch.as_tensor(Y, device="cuda")
+    for call in (lambda: ctx.mlp_predict(Xd), lambda: ctx.mlp_gradient(Xd, Yd)):
+        with pytest.raises(bh.BHError) as e:
+            call()
+        assert e.value.status == bh.BH_ESTATE
+    for bad in (dict(theta_min=-0.1), dict(theta_max=float("nan")), dict(tau=float("inf"))):
+        with pytest.raises(bh.BHError) as e:
+            ctx.set_params(**bad)
+        assert e.value.status == bh.BH_EINVAL
+        assert (ctx.params.theta_min, ctx.params.theta_max, ctx.params.tau) == (0.2, 1.0, 1e-3)
+    ctx.set_params(theta_min=0.3)
+    ctx.mlp_weights(set=_weights(X, Y, 10))
+    pred = ctx.mlp_predict(Xd).cpu().numpy()
+    assert np.isfinite(pred).all()
+    ctx.close()
