@@ -20,7 +20,10 @@
  * Memory and ownership
  *   - Particle arrays (bh_system) are DEVICE pointers owned by the caller,
  *     FP64, structure-of-arrays, one entry per particle in the caller's
- *     order.  The library never keeps a caller pointer past the call.
+ *     order.  The library reads and writes them only inside the calls
+ *     that take them, with one exception: bh_step_continue writes its
+ *     results to the arrays of the bh_step (or bh_build_tree) that started
+ *     the integration.
  *   - The context owns every derived structure (sorted copy of the
  *     particles, keys, tree, groups, lists, scratch) in device memory it
  *     allocates itself.  bh_destroy frees it.
@@ -222,8 +225,8 @@ bh_status bh_step(bh_ctx *ctx, const bh_system *sys, int32_t n_sys, double dt,
  * + bh_make_lists + bh_forces, with velocities) from the context's internal
  * state: n_steps more kick-drift-kick steps, the rebuild schedule carried on
  * from the previous call (a build every rebuild_every force evaluations).
- * The caller's arrays of that call are written at the end, and must not be
- * changed by the caller in between (use bh_step to start over).  BH_ESTATE
+ * The caller's arrays of that call are written at the end: they must stay
+ * allocated and unchanged in between (use bh_step to start over).  BH_ESTATE
  * if there is no state to continue. */
 bh_status bh_step_continue(bh_ctx *ctx, double dt, int32_t n_steps, int32_t rebuild_every, void *stream);
 

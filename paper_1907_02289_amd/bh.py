@@ -140,7 +140,7 @@ class Context:
         h = C.c_void_p()
         self._check(self.L.bh_create(C.byref(h), C.byref(self.params)), ctx=None)
         self.h = h
-        self._keep = []
+        self._keep = []       # the systems whose arrays bh_step_continue writes
 
     def _check(self, st, ctx="self"):
         if st != BH_OK:
@@ -182,6 +182,7 @@ class Context:
         arr = self._systems(systems)
         self._check(self.L.bh_build_tree(self.h, arr, len(systems), _stream()))
         self._sizes = [s["x"].numel() for s in systems]
+        self._keep = list(systems)
 
     def make_lists(self):
         self._check(self.L.bh_make_lists(self.h, _stream()))
@@ -205,6 +206,7 @@ class Context:
         self._check(self.L.bh_step(self.h, arr, len(systems), float(dt), int(n_steps), int(rebuild_every),
                                    _stream()))
         self._sizes = [s["x"].numel() for s in systems]
+        self._keep = list(systems)
 
     def step_continue(self, dt, n_steps, rebuild_every=1):
         self._check(self.L.bh_step_continue(self.h, float(dt), int(n_steps), int(rebuild_every), _stream()))
