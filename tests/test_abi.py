@@ -53,3 +53,15 @@ def test_binding_rejects_tensors_the_library_cannot_take():
     for t in (torch.zeros(4, dtype=torch.float64), torch.zeros(4, dtype=torch.float32), [0.0] * 4):
         with pytest.raises(TypeError):
             bh._ptr(t, 4, "x")
+
+
+def test_bench_uses_the_papers_printed_values():
+    """The benchmark's paper-convention flop count and its collision
+    restitution are the values the paper prints (tests/golden)."""
+    import inspect
+
+    import bench
+    from golden import paper_values
+    pv = paper_values()
+    assert bench.PAPER_FLOPS_PER_INTERACTION == pv["flops_particle_cell"]
+    assert inspect.signature(bench.collision_params).parameters["restitution"].default == pv["restitution_radial"]

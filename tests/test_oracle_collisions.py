@@ -20,7 +20,11 @@ import numpy as np
 import pytest
 
 import oracle
+from golden import paper_values
 from paper_1907_02289_amd import inputs
+
+# the paper's radial coefficient of restitution (Sec. 5.1)
+E_PAPER = paper_values()["restitution_radial"]
 
 
 def contact_params(t_c, e):
@@ -56,7 +60,7 @@ def head_on(m1, m2, rc, kappa, eta, v_in, dt, G=0.0):
 
 @pytest.mark.parametrize("m1,m2", [(1.0, 1.0), (1.0, 3.0), (0.25, 2.0)])
 def test_restitution_and_contact_time(m1, m2):
-    rc, t_c, e = 1e-2, 1.0, 0.5
+    rc, t_c, e = 1e-2, 1.0, E_PAPER
     kappa, eta = contact_params(t_c, e)
     e_num, tc_num, dp = head_on(m1, m2, rc, kappa, eta, v_in=1e-2, dt=5e-4)
     assert abs(e_num - e) <= 6e-4, e_num
@@ -75,8 +79,8 @@ def test_elastic_contact_keeps_speed():
 def test_restitution_converges_with_step():
     # the leapfrog's error in e shrinks as dt does (the dashpot sees
     # half-kicked velocities): halving dt must at least halve it
-    rc, kappa, eta = 1e-2, *contact_params(1.0, 0.5)
-    errs = [abs(head_on(1.0, 1.0, rc, kappa, eta, 1e-2, dt)[0] - 0.5) for dt in (8e-3, 4e-3, 2e-3)]
+    rc, kappa, eta = 1e-2, *contact_params(1.0, E_PAPER)
+    errs = [abs(head_on(1.0, 1.0, rc, kappa, eta, 1e-2, dt)[0] - E_PAPER) for dt in (8e-3, 4e-3, 2e-3)]
     assert errs[1] <= 0.6 * errs[0] and errs[2] <= 0.6 * errs[1], errs
 
 
