@@ -65,3 +65,12 @@ def test_bench_uses_the_papers_printed_values():
     pv = paper_values()
     assert bench.PAPER_FLOPS_PER_INTERACTION == pv["flops_particle_cell"]
     assert inspect.signature(bench.collision_params).parameters["restitution"].default == pv["restitution_radial"]
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """Without the built library the binding raises: there is no other
+    implementation to fall back on."""
+    from paper_1907_02289_amd import bh
+    monkeypatch.setattr(bh, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        bh.load_library(str(tmp_path / "libbh.so"))
