@@ -357,11 +357,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
     ap.add_argument("--no-collisions", action="store_true", help="skip timing the collision branch")
     ap.add_argument("--match-along-run", action="store_true",
-                    help="match theta on the largest p99 over the first --error-evals force evaluations of each "
-                         "path's run instead of on the first one")
-    ap.add_argument("--error-evals", type=int, default=32,
-                    help="force evaluations of the untimed run that reports the tuned path's error along its "
-                         "trajectory (0: skip)")
+                    help="match theta on the largest p99 over the force evaluations of the error run (see "
+                         "--error-evals) instead of on the first one")
+    ap.add_argument("--error-evals", type=int, default=None,
+                    help="force evaluations of the untimed runs that report each path's error along its "
+                         "trajectory (default: through the last timed evaluation of the tuned path; 0: skip)")
     ap.add_argument("--reuse-study", action="store_true",
                     help="only the list-reuse study: matched-error theta and time per step for each rebuild interval")
     ap.add_argument("--learned", action="store_true",
@@ -384,6 +384,9 @@ def main():
     sysm = w.systems[0]
     n = sysm.n
     R = w.rebuild_every
+    if args.error_evals is None:
+        # the first evaluation, the warm-up cycles and the timed cycles
+        args.error_evals = 1 + R * (args.warmup + args.steps)
     log(f"[bench] ring n={n} rebuild_every={R}")
     dev0 = bh.to_device(sysm)
     sample = torch.as_tensor(inputs.force_sample(n, 3).astype(np.int64), device="cuda")
