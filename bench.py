@@ -44,6 +44,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def p99_nearest_rank(e):
+    """The 99th percentile by nearest rank: the ceil(0.99 n)-th smallest of n values."""
+    e = np.asarray(e)
+    return float(np.sort(e)[int(math.ceil(0.99 * e.size)) - 1])
+
+
 def rel_err_p99(ctx, dev, targets, ref, n):
     import torch
     # potentials requested too: the tuning launches use the potential-computing
@@ -54,8 +60,7 @@ def rel_err_p99(ctx, dev, targets, ref, n):
     a = torch.stack([out["ax"][targets], out["ay"][targets], out["az"][targets]])
     r = torch.stack([ref["ax"], ref["ay"], ref["az"]])
     e = (torch.linalg.vector_norm(a - r, dim=0) / torch.linalg.vector_norm(r, dim=0)).cpu().numpy()
-    k = int(math.ceil(0.99 * e.size)) - 1            # nearest-rank percentile
-    return float(np.sort(e)[k]), float(np.median(e))
+    return p99_nearest_rank(e), float(np.median(e))
 
 
 def tune_theta(ctx, dev, targets, ref, n, lo=0.1, hi=1.0, iters=10):
@@ -109,7 +114,7 @@ def error_run(bh, w, dev0, sample, p, n_evals):
         a = a + gmc * pos / (np.sum(pos * pos, 1) ** 1.5)[:, None]
         r = np.stack([ref[f].cpu().numpy() for f in ("ax", "ay", "az")], 1)
         e = np.linalg.norm(a - r, axis=1) / np.linalg.norm(r, axis=1)
-        out.append(float(np.sort(e)[int(math.ceil(0.99 * e.size)) - 1]))
+        out.append(p99_nearest_rank(e))
         med.append(float(np.median(e)))
         del acc
     ctx.close()
@@ -219,7 +224,7 @@ def reuse_study(bh, w, dev0, sample, n, n_group, steps, cyl_radius=0.0, theta_lo
                              out["az"][sample] + gmc * z / r3])
             r = torch.stack([ref["ax"], ref["ay"], ref["az"]])
             e = (torch.linalg.vector_norm(a - r, dim=0) / torch.linalg.vector_norm(r, dim=0)).cpu().numpy()
-            errs.append(float(np.sort(e)[int(math.ceil(0.99 * e.size)) - 1]))
+            errs.append(p99_nearest_rank(e))
         inter = ctx.query()["interactions"]
         ctx.close()
         del dev

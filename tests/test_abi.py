@@ -74,3 +74,16 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(bh, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         bh.load_library(str(tmp_path / "libbh.so"))
+
+
+def test_bench_percentile_is_nearest_rank():
+    """p99 by nearest rank: of 100 values the 99th smallest, of 4096 the
+    4056th (ceil(0.99 * 4096) = 4056), of 1 value that value."""
+    import numpy as np
+
+    import bench
+    v = np.arange(1, 101, dtype=float)[::-1].copy()
+    assert bench.p99_nearest_rank(v) == 99.0
+    w = np.random.default_rng(0).permutation(4096).astype(float)
+    assert bench.p99_nearest_rank(w) == 4055.0
+    assert bench.p99_nearest_rank(np.array([3.5])) == 3.5
