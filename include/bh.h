@@ -305,6 +305,14 @@ bh_status bh_mlp_weights(bh_ctx *ctx, float *get, const float *set);
 bh_status bh_mlp_dataset(bh_ctx *ctx, int64_t *n, uint32_t *pairs, float *x, float *y);
 bh_status bh_mlp_clear(bh_ctx *ctx);
 
+/* Replace the training set with n pairs from host memory, in the layout
+ * bh_mlp_dataset returns: pairs uint32[n][2] (group, node; may be NULL,
+ * then zeros), features float[n][4] and labels float[n] on the scale the
+ * network predicts.  For training on pairs gathered elsewhere, e.g. by a
+ * CPU reference.  BH_EINVAL if n < 1 or n >= 2^31 or x or y is NULL; the
+ * arrays are copied before the call returns. */
+bh_status bh_mlp_set_dataset(bh_ctx *ctx, int64_t n, const uint32_t *pairs, const float *x, const float *y);
+
 /* Network output for n feature rows (device float[n][4] -> device float[n]).
  * BH_ESTATE until weights are set (bh_mlp_weights) or trained. */
 bh_status bh_mlp_predict(bh_ctx *ctx, const float *x, int64_t n, float *out, void *stream);

@@ -25,8 +25,8 @@ STAGES = ("keys_sort", "tree", "moments", "groups", "walk", "forces", "integrate
 SYMBOLS = ("bh_create", "bh_destroy", "bh_set_params", "bh_build_tree", "bh_make_lists", "bh_forces",
            "bh_step", "bh_step_continue", "bh_direct_sum", "bh_force_timing", "bh_query", "bh_export",
            "bh_export_groups", "bh_stage_times", "bh_autotune", "bh_mlp_collect", "bh_mlp_train",
-           "bh_mlp_weights", "bh_mlp_dataset", "bh_mlp_clear", "bh_mlp_predict", "bh_mlp_gradient",
-           "bh_last_error")
+           "bh_mlp_weights", "bh_mlp_dataset", "bh_mlp_clear", "bh_mlp_set_dataset", "bh_mlp_predict",
+           "bh_mlp_gradient", "bh_last_error")
 
 
 class Params(C.Structure):
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH):
     L.bh_mlp_weights.argtypes = [vp, vp, vp]
     L.bh_mlp_dataset.argtypes = [vp, C.POINTER(C.c_int64), vp, vp, vp]
     L.bh_mlp_clear.argtypes = [vp]
+    L.bh_mlp_set_dataset.argtypes = [vp, C.c_int64, vp, vp, vp]
     L.bh_mlp_predict.argtypes = [vp, vp, C.c_int64, vp, vp]
     L.bh_mlp_gradient.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.bh_query.argtypes = [vp, C.POINTER(Sizes)]
@@ -263,6 +264,21 @@ class Context:
 
     def mlp_clear(self):
         self._check(self.L.bh_mlp_clear(self.h))
+
+    def mlp_set_dataset(self, X, Y, pairs=None):
+        """Replace the training set: features X (n x 4), labels Y (n), and
+        optionally the (group, node) pairs (n x 2), all host arrays."""
+        X = np.ascontiguousarray(X, np.float32).reshape(-1, 4)
+        Y = np.ascontiguousarray(Y, np.float32).reshape(-1)
+        if Y.size != X.shape[0]:
+            raise ValueError(f"mlp_set_dataset: {X.shape[0]} feature rows, {Y.size} labels")
+        P = None
+        if pairs is not None:
+            P = np.ascontiguousarray(pairs, np.uint32).reshape(-1, 2)
+            if P.shape[0] != X.shape[0]:
+                raise ValueError(f"mlp_set_dataset: {P.shape[0]} pairs for {X.shape[0]} rows")
+        self._check(self.L.bh_mlp_set_dataset(self.h, X.shape[0], None if P is None else P.ctypes.data_as(C.c_void_p),
+                                               X.ctypes.data_as(C.c_void_p), Y.ctypes.data_as(C.c_void_p)))
 
     def mlp_predict(self, X):
         import torch

@@ -26,6 +26,9 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// per-block partial sums of the scans (at least the scan kernels' block count)
+constexpr size_t SCAN_TMP_WORDS = 4096;
+
 enum StageEv { EV_KEYS = 0, EV_TREE, EV_MOM, EV_GROUPS, EV_WALK, EV_FORCE, EV_INTEG, EV_STEP, EV_N };
 
 }  // namespace
@@ -318,7 +321,7 @@ bh_status ensure_particles(bh_ctx *c, uint32_t n) {
     HIPCHK(c, grow(c->val, u4));
     HIPCHK(c, grow(c->val_tmp, u4));
     HIPCHK(c, grow(c->hist, bhk::radix_hist_words(cap) * 4));
-    HIPCHK(c, grow(c->scan_tmp, 4096 * 4));
+    HIPCHK(c, grow(c->scan_tmp, SCAN_TMP_WORDS * 4));
     HIPCHK(c, grow(c->gmark, u4));
     HIPCHK(c, grow(c->grp, (size_t)cap * sizeof(GroupInfo)));
     HIPCHK(c, grow(c->g_lo, (size_t)cap * sizeof(int4)));
@@ -986,6 +989,9 @@ bh_status ensure_mlp_train_buffers(bh_ctx *c, uint32_t B, uint64_t n) {
     HIPCHK(c, grow(c->pv_a, std::max<uint64_t>(n, B) * 4));
     HIPCHK(c, grow(c->pv_b, std::max<uint64_t>(n, B) * 4));
     HIPCHK(c, grow(c->phist, bhk::radix_hist_words((uint32_t)std::max<uint64_t>(n, B)) * 4));
+    // the epoch shuffle's sort scans with it; a context that never built a
+    // tree (training on a set from bh_mlp_set_dataset) has none yet
+    HIPCHK(c, grow(c->scan_tmp, SCAN_TMP_WORDS * 4));
     return BH_OK;
 }
 
@@ -1110,6 +1116,27 @@ bh_status bh_mlp_dataset(bh_ctx *c, int64_t *n, uint32_t *pairs, float *x, float
 bh_status bh_mlp_clear(bh_ctx *c) {
     if (!c) return BH_EINVAL;
     c->ds_n = 0;
+    return BH_OK;
+}
+
+bh_status bh_mlp_set_dataset(bh_ctx *c, int64_t n, const uint32_t *pairs, const float *x, const float *y) {
+    if (!c) return BH_EINVAL;
+    if (n < 1 || n >= (1ll << 31) || !x || !y) return fail(c, BH_EINVAL, "bh_mlp_set_dataset: bad arguments");
+    const uint64_t un = (uint64_t)n;
+    HIPCHK(c, hipDeviceSynchronize());
+    if (un > c->ds_cap) {
+        HIPCHK(c, grow(c->ds_x, un * sizeof(float4)));
+        HIPCHK(c, grow(c->ds_y, un * 4));
+        HIPCHK(c, grow(c->ds_pairs, un * sizeof(uint2)));
+        c->ds_cap = un;
+    }
+    HIPCHK(c, hipMemcpy(c->ds_x.p, x, un * sizeof(float4), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ds_y.p, y, un * 4, hipMemcpyHostToDevice));
+    if (pairs)
+        HIPCHK(c, hipMemcpy(c->ds_pairs.p, pairs, un * sizeof(uint2), hipMemcpyHostToDevice));
+    else
+        HIPCHK(c, hipMemset(c->ds_pairs.p, 0, un * sizeof(uint2)));
+    c->ds_n = un;
     return BH_OK;
 }
 

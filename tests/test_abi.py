@@ -87,3 +87,15 @@ def test_bench_percentile_is_nearest_rank():
     w = np.random.default_rng(0).permutation(4096).astype(float)
     assert bench.p99_nearest_rank(w) == 4055.0
     assert bench.p99_nearest_rank(np.array([3.5])) == 3.5
+
+
+def test_binding_checks_a_supplied_training_set():
+    """mlp_set_dataset refuses features, labels and pairs of different
+    lengths before the library is called."""
+    import numpy as np
+    from paper_1907_02289_amd import bh
+    ctx = bh.Context.__new__(bh.Context)          # no library context: the checks come first
+    with pytest.raises(ValueError):
+        ctx.mlp_set_dataset(np.zeros((5, 4)), np.zeros(4))
+    with pytest.raises(ValueError):
+        ctx.mlp_set_dataset(np.zeros((5, 4)), np.zeros(5), pairs=np.zeros((4, 2)))

@@ -151,3 +151,23 @@ def test_parameters_and_calls_without_weights(torch_cuda):
     pred = ctx.mlp_predict(Xd).cpu().numpy()
     assert np.isfinite(pred).all()
     ctx.close()
+
+
+def test_training_on_a_supplied_set_without_a_tree(torch_cuda):
+    """A context that never built a tree trains on a set given through
+    bh_mlp_set_dataset (the training's epoch shuffle sorts with scratch that
+    a tree build used to be the only one to allocate): the set reads back
+    unchanged, and training brings the error well below the label variance."""
+    from paper_1907_02289_amd import bh
+    _log("[gpu] learned network: training on a supplied set, no tree")
+    X, Y = _synthetic(6000, 11)
+    ctx = bh.Context(theta=0.5, eps=1e-3, n_group=64, criterion=bh.LEARNED)
+    ctx.mlp_set_dataset(X, Y)
+    pairs, X2, Y2 = ctx.mlp_dataset()
+    np.testing.assert_array_equal(X2, X)
+    np.testing.assert_array_equal(Y2, Y)
+    assert pairs.shape == (6000, 2) and not pairs.any()
+    mse = ctx.mlp_train(iters=300, batch=1024, seed=1)
+    _log(f"    mse {mse:.4f}, label variance {Y.var():.4f}")
+    assert np.isfinite(mse) and mse < 0.5 * Y.var()
+    ctx.close()
