@@ -170,3 +170,103 @@ def test_learned_walk_limits(bias, theta_ref):
         pp_got = got[3][got[2][g]:got[2][g + 1]].tolist()
         assert pc_got == sorted(pc_ref | moved)
         assert pp_got == sorted(pp_ref - moved)
+
+
+def _band_walk_py(st, t, com4, gamin, g, th_min, th_max, y0, tau, G, cap=65536):
+    """The learned walk of one group restated from its definition, with the
+    network held at the constant output y0: a node in the band
+    th_min <= side/d_box < th_max with 2..cap particles is accepted when the
+    error the network predicts, 2^y0 G M / d^2 (d = distance of the node's
+    centre of mass from the group centre), is below tau A_g.  Returns the
+    node list, the particle list and the band decisions {node: (accepted,
+    threshold tau at which the decision flips)}."""
+    pc, pp, band = [], [], {}
+    stack = [0]
+    gb = st.gbox[g]
+    cen = np.asarray(st.gcen[g], np.float64)
+    while stack:
+        v = stack.pop()
+        lvl, pfx, cnt = int(t["level"][v]), int(t["prefix"][v]), int(t["count"][v])
+        if _accept_exact(gb, lvl, pfx, th_min):
+            acc = True
+        elif not _accept_exact(gb, lvl, pfx, th_max):
+            acc = False
+        elif cnt == 1:
+            acc = True
+        elif cnt > cap:
+            acc = _accept_exact(gb, lvl, pfx, 0.0)
+        else:
+            dvec = com4[v, :3] - cen
+            d2 = float(dvec @ dvec)
+            M = float(com4[v, 3])
+            predicted = 2.0 ** y0 * G * M / d2          # the predicted absolute error
+            acc = predicted < tau * gamin[g]
+            band[v] = (acc, predicted / gamin[g])
+        if acc:
+            pc.append(v)
+        elif t["n_child"][v] == 0:
+            pp.append(v)
+        else:
+            fc = int(t["first_child"][v])
+            stack.extend(range(fc, fc + int(t["n_child"][v])))
+    return sorted(pc), sorted(pp), band
+
+
+def _const_net(y0):
+    """Weights whose output is exactly y0 (an integer) for every input."""
+    w = np.zeros(1259, np.float32)
+    w[1253:1257] = 1.0
+    w[mlp.B3] = y0
+    w[1258] = 1.0
+    return w
+
+
+def test_learned_acceptance_threshold():
+    """The band decision of the learned walk against its definition (error
+    budget tau * A_g on the predicted absolute error 2^y G M / d^2), with G,
+    A_g and the masses chosen so that a misplaced factor changes decisions.
+    Every band decision of the oracle must equal the one restated here; and
+    for band nodes picked from several groups, tau set 0.5% above / below
+    the node's own flip point must accept / open it."""
+    st, t, com4, qn, grad, gamin = _setup(n=1500, seed=3, n_grp=32)
+    rng = np.random.default_rng(11)
+    gamin = rng.uniform(0.05, 2.0, gamin.size)         # a different budget scale per group
+    G, y0 = 2.5, -7
+    th_min, th_max = 0.25, 0.9
+    w = _const_net(y0)
+    ng = st.gnode.size
+
+    def oracle_lists(tau):
+        return oracle.lists_learned(st.gbox, st.gcen, grad, gamin, t, com4, qn, w, st.S, theta=0.5,
+                                    theta_min=th_min, theta_max=th_max, tau=tau, G=G)
+
+    # flip points of every band pair at a middle tau: accept iff tau > flip
+    tau0 = 3e-3
+    flips = {}
+    n_acc = n_rej = 0
+    got = oracle_lists(tau0)
+    for g in range(ng):
+        pc, pp, band = _band_walk_py(st, t, com4, gamin, g, th_min, th_max, y0, tau0, G)
+        assert got[1][got[0][g]:got[0][g + 1]].tolist() == pc, g
+        assert got[3][got[2][g]:got[2][g + 1]].tolist() == pp, g
+        for v, (acc, flip) in band.items():
+            n_acc += acc
+            n_rej += not acc
+            flips[(g, v)] = flip
+    assert n_acc > 20 and n_rej > 20, (n_acc, n_rej)
+
+    # straddle single pairs: groups where that node is reached at both taus
+    picked = 0
+    for (g, v), flip in sorted(flips.items(), key=lambda kv: kv[1])[:: max(1, len(flips) // 12)]:
+        for factor, want in ((1.005, True), (1 / 1.005, False)):
+            tau = flip * factor
+            pc, pp, band = _band_walk_py(st, t, com4, gamin, g, th_min, th_max, y0, tau, G)
+            if v not in band:
+                break                                    # an ancestor flipped first: not reached
+            assert band[v][0] == want
+            lo = oracle_lists(tau)
+            in_pc = v in set(lo[1][lo[0][g]:lo[0][g + 1]].tolist())
+            assert in_pc == want, (g, v, factor)
+        else:
+            picked += 1
+    assert picked >= 5, picked
