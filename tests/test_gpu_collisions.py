@@ -12,6 +12,8 @@ import sys
 
 import numpy as np
 import pytest
+
+from bars import fp32_bars
 from scipy.spatial import cKDTree
 
 import oracle
@@ -100,8 +102,8 @@ def test_forces_with_contacts(torch_cuda, name, n, seed, theta, eps, n_grp, rc, 
         relm = err[moved] / mag[moved]
         _log(f"    fp32 rel err: median {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e} max {rel.max():.2e}; "
              f"particles in contact: max err/term sum {relm.max():.2e}")
-        assert np.median(rel) <= 1e-5
-        assert np.median(relm) <= 1e-5
+        fp32_bars(rel, "all particles")
+        assert np.median(relm) <= 1e-5 and relm.max() <= 1e-4, (np.median(relm), relm.max())
     ctx.close()
 
 
@@ -229,7 +231,7 @@ def test_contacts_with_cylindrical_tree_and_two_systems(torch_cuda, precision):
         else:
             rel = err / np.sqrt(ax ** 2 + ay ** 2 + az ** 2)
             _log(f"    n={s.n}: fp32 rel err median {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e}")
-            assert np.median(rel) <= 1e-5
+            fp32_bars(rel, f"n={s.n}")
     ctx.close()
 
 

@@ -8,6 +8,8 @@ import sys
 import numpy as np
 import pytest
 
+from bars import fp32_bars
+
 import oracle
 from paper_1907_02289_amd import inputs
 from test_gpu_parity import _compare_structures
@@ -62,7 +64,7 @@ def test_cylindrical_structures_and_forces(torch_cuda, name, make, r_ref, theta,
     else:
         rel = err / np.sqrt(ax ** 2 + ay ** 2 + az ** 2)
         _log(f"    fp32 rel err: median {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e}")
-        assert np.median(rel) <= 1e-5
+        fp32_bars(rel, name)
     ctx.close()
 
 
