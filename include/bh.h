@@ -244,6 +244,18 @@ bh_status bh_step_continue(bh_ctx *ctx, double dt, int32_t n_steps, int32_t rebu
 bh_status bh_direct_sum(bh_ctx *ctx, const bh_system *sys, const int64_t *targets, int64_t n_targets,
                         double *ax, double *ay, double *az, void *stream);
 
+/* Accelerations of the last force evaluation (bh_forces, bh_step,
+ * bh_step_continue) for chosen particles of one system, without copying the
+ * rest: for t < n_targets, (ax, ay, az)[t] = acceleration of caller index
+ * targets[t] of system sys, as bh_forces writes it (self-gravity plus the
+ * central mass term).  targets, ax, ay, az: device arrays of n_targets
+ * entries.  An index outside [0, n) of the system gives NaN; nothing outside
+ * the arrays is read.  BH_ESTATE before a force evaluation; does not
+ * synchronise.  For judging the error of a running integration against
+ * bh_direct_sum at the same positions. */
+bh_status bh_sample_acc(bh_ctx *ctx, int32_t sys, const int64_t *targets, int64_t n_targets, double *ax,
+                        double *ay, double *az, void *stream);
+
 /* Force-kernel device time accumulated over the launches since the last
  * reset, from HIP events recorded around each launch on its stream
  * (synchronises those events).  reset != 0 clears the accumulator after
@@ -296,8 +308,22 @@ typedef struct {
 bh_status bh_mlp_train(bh_ctx *ctx, const bh_train_opts *o, double *mse, void *stream);
 
 /* Copy the weights out (get, host, BH_MLP_NPARAM floats) and/or install new
- * ones (set); either may be NULL.  Installing weights invalidates lists. */
+ * ones (set); either may be NULL.  Installing weights invalidates lists and
+ * restarts the optimiser: Adam's moment estimates and step count return to
+ * zero. */
 bh_status bh_mlp_weights(bh_ctx *ctx, float *get, const float *set);
+
+/* One Adam step (Kingma & Ba 2015) on the first 1249 weights with the
+ * gradient grad (device float[1249]): with t the steps since the weights
+ * were installed or initialised,
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   w -= lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps),
+ * in FP32.  The step bh_mlp_train takes after each batch gradient; exposed
+ * for callers that compute gradients themselves.  BH_EINVAL for lr <= 0 or
+ * betas outside [0, 1); BH_ESTATE until weights are set or trained.
+ * Invalidates lists.  Does not synchronise. */
+bh_status bh_mlp_adam(bh_ctx *ctx, const float *grad, float lr, float beta1, float beta2, float eps,
+                      void *stream);
 
 /* Training-set size, and optionally its pairs (uint32[n][2] group, node of
  * the tree they were collected on), features (float[n][4]) and labels

@@ -26,7 +26,7 @@ SYMBOLS = ("bh_create", "bh_destroy", "bh_set_params", "bh_build_tree", "bh_make
            "bh_step", "bh_step_continue", "bh_direct_sum", "bh_force_timing", "bh_query", "bh_export",
            "bh_export_groups", "bh_stage_times", "bh_autotune", "bh_mlp_collect", "bh_mlp_train",
            "bh_mlp_weights", "bh_mlp_dataset", "bh_mlp_clear", "bh_mlp_set_dataset", "bh_mlp_predict",
-           "bh_mlp_gradient", "bh_last_error")
+           "bh_mlp_gradient", "bh_mlp_adam", "bh_sample_acc", "bh_last_error")
 
 
 class Params(C.Structure):
@@ -81,6 +81,7 @@ def load_library(path: str = LIB_PATH):
     L.bh_step.argtypes = [vp, C.POINTER(System), i32, dbl, i32, i32, vp]
     L.bh_step_continue.argtypes = [vp, dbl, i32, i32, vp]
     L.bh_direct_sum.argtypes = [vp, C.POINTER(System), vp, C.c_int64, vp, vp, vp, vp]
+    L.bh_sample_acc.argtypes = [vp, i32, vp, C.c_int64, vp, vp, vp, vp]
     L.bh_force_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
     L.bh_autotune.argtypes = [vp, C.POINTER(C.c_int32), i32, i32, C.POINTER(C.c_int32), vp]
     L.bh_mlp_collect.argtypes = [vp, i32, i32, vp]
@@ -91,6 +92,7 @@ def load_library(path: str = LIB_PATH):
     L.bh_mlp_set_dataset.argtypes = [vp, C.c_int64, vp, vp, vp]
     L.bh_mlp_predict.argtypes = [vp, vp, C.c_int64, vp, vp]
     L.bh_mlp_gradient.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    L.bh_mlp_adam.argtypes = [vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     L.bh_query.argtypes = [vp, C.POINTER(Sizes)]
     L.bh_export.argtypes = [vp, i32, vp, vp]
     L.bh_export_groups.argtypes = [vp, vp, vp, vp]
@@ -224,6 +226,18 @@ class Context:
                                          _ptr(out["ax"], nt, "ax"), _ptr(out["ay"], nt, "ay"),
                                          _ptr(out["az"], nt, "az"), _stream()))
 
+    def sample_acc(self, targets, out, system=0):
+        """Accelerations of the last force evaluation at caller indices
+        targets (int64 CUDA tensor) of one system into out (dict of ax, ay,
+        az tensors of len(targets))."""
+        import torch
+        if not (targets.is_cuda and targets.dtype == torch.int64 and targets.is_contiguous()):
+            raise TypeError("targets: need a contiguous CUDA int64 tensor")
+        nt = targets.numel()
+        self._check(self.L.bh_sample_acc(self.h, int(system), C.c_void_p(targets.data_ptr()), nt,
+                                         _ptr(out["ax"], nt, "ax"), _ptr(out["ay"], nt, "ay"),
+                                         _ptr(out["az"], nt, "az"), _stream()))
+
     def autotune(self, candidates=(64, 128, 256, 512), rebuild_every=4):
         arr = (C.c_int32 * len(candidates))(*candidates)
         out = C.c_int32()
@@ -302,6 +316,14 @@ class Context:
                                            X.shape[0], C.c_void_p(grad.data_ptr()), C.c_void_p(loss.data_ptr()),
                                            _stream()))
         return grad, loss
+
+    def mlp_adam(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam step of the weights with grad (CUDA float32 tensor of 1249)."""
+        import torch
+        if not (isinstance(grad, torch.Tensor) and grad.is_cuda and grad.dtype == torch.float32
+                and grad.is_contiguous() and grad.numel() == 1249):
+            raise TypeError("mlp_adam: need a contiguous CUDA float32 tensor of 1249 values")
+        self._check(self.L.bh_mlp_adam(self.h, C.c_void_p(grad.data_ptr()), lr, beta1, beta2, eps, _stream()))
 
     def force_timing(self, reset=True):
         """(total ms, launches) of the force kernel since the last reset."""

@@ -478,11 +478,26 @@ bh_status walk_until_fits(bh_ctx *c, hipStream_t s) {
         ev_end(c, EV_WALK, s);
         STCHK(read_counters(c, s));
         const DevCounters &h = *c->h_cnt;
+        if (h.flags[FLAG_WALK_BOUND]) {
+            c->lists_valid = false;
+            return fail(c, BH_ECAPACITY, "walk: a traversal went deeper than the tree's levels or visited more "
+                                         "nodes than the tree holds (malformed tree)");
+        }
         if (h.flags[FLAG_WALK_OVF]) {
             if (attempt > 40) return fail(c, BH_ECAPACITY, "walk scratch cannot grow further");
-            // a walk cut short by its frontier may also need a longer list: that shows on the next try
-            if (h.walk_need_front >= c->walk_front) c->walk_front = std::max(2 * c->walk_front, 2 * h.walk_need_front);
-            if (h.walk_need_list >= c->walk_list) c->walk_list = std::max(2 * c->walk_list, 2 * h.walk_need_list);
+            // a walk cut short by its frontier may also need a longer list: that shows on the next try.
+            // Neither a frontier nor a list of a well-formed tree holds more entries than the tree has nodes.
+            const uint64_t most = (uint64_t)c->n_nodes + 64;
+            if (h.walk_need_front > most || h.walk_need_list > most)
+                return fail(c, BH_ECAPACITY, "walk: frontier or list longer than the tree's node count");
+            auto grown = [most](uint32_t cur, uint32_t need) {
+                return (uint32_t)std::min<uint64_t>(most, std::max<uint64_t>(2ull * cur, 2ull * need));
+            };
+            const uint32_t f0 = c->walk_front, l0 = c->walk_list;
+            if (h.walk_need_front >= c->walk_front) c->walk_front = grown(c->walk_front, h.walk_need_front);
+            if (h.walk_need_list >= c->walk_list) c->walk_list = grown(c->walk_list, h.walk_need_list);
+            if (c->walk_front == f0 && c->walk_list == l0)
+                return fail(c, BH_ECAPACITY, "walk scratch overflow without a larger need");
             STCHK(ensure_walk(c));
             continue;
         }
@@ -891,6 +906,19 @@ bh_status bh_direct_sum(bh_ctx *c, const bh_system *sys, const int64_t *targets,
     return BH_OK;
 }
 
+bh_status bh_sample_acc(bh_ctx *c, int32_t sys, const int64_t *targets, int64_t n_targets, double *ax, double *ay,
+                        double *az, void *stream) {
+    if (!c) return BH_EINVAL;
+    if (!c->state_valid) return fail(c, BH_ESTATE, "bh_sample_acc: no force evaluation to read");
+    if (sys < 0 || sys >= c->n_sys || n_targets < 0) return fail(c, BH_EINVAL, "bh_sample_acc: bad system or count");
+    if (n_targets > 0 && (!targets || !ax || !ay || !az))
+        return fail(c, BH_EINVAL, "bh_sample_acc: null target or output array");
+    refresh_state(c);
+    bhk::sample_acc(c->d, sys, targets, n_targets, ax, ay, az, (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return BH_OK;
+}
+
 bh_status bh_force_timing(bh_ctx *c, double *total_ms, int64_t *launches, int32_t reset) {
     if (!c) return BH_EINVAL;
     double tot = 0.0;
@@ -1031,7 +1059,10 @@ bh_status bh_mlp_collect(bh_ctx *c, int32_t max_groups, int32_t count_cap, void 
     bhk::cand_features_labels(c->d, nc, P<float4>(c->ds_x) + c->ds_n, P<float>(c->ds_y) + c->ds_n, s);
     HIPCHK(c, hipMemcpyAsync(P<uint2>(c->ds_pairs) + c->ds_n, c->cand.p, nc * sizeof(uint2),
                              hipMemcpyDeviceToDevice, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+    STCHK(read_counters(c, s));
+    if (c->h_cnt->flags[FLAG_CAND_BAD])
+        return fail(c, BH_ECAPACITY, "bh_mlp_collect: a candidate pair named a group or node outside the tree "
+                                     "or a node above the particle cap; nothing was added");
     c->ds_n = need;
     return BH_OK;
 }
@@ -1096,9 +1127,28 @@ bh_status bh_mlp_weights(bh_ctx *c, float *get, const float *set) {
     if (get) HIPCHK(c, hipMemcpy(get, c->mlp_w.p, BH_MLP_NPARAM * 4, hipMemcpyDeviceToHost));
     if (set) {
         HIPCHK(c, hipMemcpy(c->mlp_w.p, set, BH_MLP_NPARAM * 4, hipMemcpyHostToDevice));
+        // new weights start a new optimisation: Adam's moments and step count from zero
+        HIPCHK(c, grow(c->mlp_m, MLP_NTRAIN * 4));
+        HIPCHK(c, grow(c->mlp_v, MLP_NTRAIN * 4));
+        HIPCHK(c, hipMemset(c->mlp_m.p, 0, MLP_NTRAIN * 4));
+        HIPCHK(c, hipMemset(c->mlp_v.p, 0, MLP_NTRAIN * 4));
+        c->adam_t = 0;
         c->mlp_ready = true;
         c->lists_valid = false;
     }
+    return BH_OK;
+}
+
+bh_status bh_mlp_adam(bh_ctx *c, const float *grad, float lr, float beta1, float beta2, float eps, void *stream) {
+    if (!c) return BH_EINVAL;
+    if (!grad || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
+        return fail(c, BH_EINVAL, "bh_mlp_adam: bad arguments");
+    if (!c->mlp_ready || !c->mlp_m.p || !c->mlp_v.p)
+        return fail(c, BH_ESTATE, "bh_mlp_adam: no weights (bh_mlp_train or bh_mlp_weights)");
+    bhk::mlp_adam(P<float>(c->mlp_w), grad, P<float>(c->mlp_m), P<float>(c->mlp_v), lr, beta1, beta2, eps,
+                  ++c->adam_t, (hipStream_t)stream);
+    c->lists_valid = false;
+    HIPCHK(c, hipGetLastError());
     return BH_OK;
 }
 
@@ -1125,6 +1175,10 @@ bh_status bh_mlp_set_dataset(bh_ctx *c, int64_t n, const uint32_t *pairs, const 
     const uint64_t un = (uint64_t)n;
     HIPCHK(c, hipDeviceSynchronize());
     if (un > c->ds_cap) {
+        // the set is empty until all three buffers hold the new size: a
+        // failed allocation leaves no count that points past a buffer
+        c->ds_n = 0;
+        c->ds_cap = 0;
         HIPCHK(c, grow(c->ds_x, un * sizeof(float4)));
         HIPCHK(c, grow(c->ds_y, un * 4));
         HIPCHK(c, grow(c->ds_pairs, un * sizeof(uint2)));

@@ -92,9 +92,34 @@ __global__ void k_scatter_acc(DevState d, const bhk::AccPtr *tab) {
     }
 }
 
+// Accelerations of chosen caller-order particles of one system, read
+// through the inverse permutation; an index outside the system gives NaN.
+__global__ void k_sample_acc(DevState d, int sys, const int64_t *targets, int64_t nt, double *ax, double *ay,
+                             double *az) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const int64_t i = targets[t];
+    const uint32_t b = d.sys_off[sys], n = d.sys_off[sys + 1] - b;
+    if (i < 0 || i >= (int64_t)n) {
+        ax[t] = ay[t] = az[t] = __builtin_nan("");
+        return;
+    }
+    const double4 a = d.acc[d.inv[b + (uint32_t)i]];
+    ax[t] = a.x;
+    ay[t] = a.y;
+    az[t] = a.z;
+}
+
 }  // namespace
 
 namespace bhk {
+
+void sample_acc(const DevState &d, int sys, const int64_t *targets, int64_t nt, double *ax, double *ay, double *az,
+                hipStream_t s) {
+    if (nt <= 0) return;
+    k_sample_acc<<<(unsigned)((nt + TPB - 1) / TPB), TPB, 0, s>>>(d, sys, targets, nt, ax, ay, az);
+}
+
 
 void kick_drift(const DevState &d, double h, double dt, hipStream_t s) {
     k_kick_drift<<<grid_for(d.n), TPB, 0, s>>>(d.pos, d.vel, d.acc, d.n, h, dt);

@@ -16,6 +16,8 @@ enum {
     FLAG_WALK_OVF = 2,          // a walk frontier/list scratch overflowed
     FLAG_POOL_OVF = 3,          // list pool capacity exceeded
     FLAG_EXTENT = 4,            // cylindrical tree coordinates exceed the root cell
+    FLAG_WALK_BOUND = 5,        // a walk went deeper than the tree's levels or visited more nodes than exist
+    FLAG_CAND_BAD = 6,          // a training candidate named a group or node outside the tree, or too many particles
     FLAG_COUNT = 8
 };
 
@@ -227,6 +229,8 @@ void kick_drift(const DevState &d, double h, double dt, hipStream_t s);
 void kick(const DevState &d, double h, hipStream_t s);
 void scatter_state(const DevState &d, hipStream_t s);
 void scatter_acc(const DevState &d, const AccPtr *tab, hipStream_t s);
+void sample_acc(const DevState &d, int sys, const int64_t *targets, int64_t nt, double *ax, double *ay, double *az,
+                hipStream_t s);
 
 // learned opening rule (bh_learned.hip)
 void node_qn(const DevState &d, hipStream_t s);

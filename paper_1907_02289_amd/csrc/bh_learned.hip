@@ -52,8 +52,22 @@ __global__ void __launch_bounds__(TPB) k_group_amin(DevState d) {
 __global__ void __launch_bounds__(TPB) k_cand(DevState d, uint64_t n_cand, float4 *X, float *Y) {
     __shared__ double4 tile[TPB];
     __shared__ double red[TPB / 64];
+    const uint32_t ng = d.cnt->n_groups, nn = d.cnt->lvl_off[BH_NLEVELS];
     for (uint64_t p = blockIdx.x; p < n_cand; p += gridDim.x) {
         const uint2 cv = d.cand[p];
+        // every loop below is bounded by the pair's group size and node
+        // count; a pair outside the tree or above the cap is not evaluated
+        const bool bad = cv.x >= ng || cv.y >= nn || d.nd_count[cv.y] > d.count_cap ||
+                         (uint64_t)d.grp[cv.x].begin + d.grp[cv.x].count > d.n ||
+                         (uint64_t)d.nd_begin[cv.y] + d.nd_count[cv.y] > d.n;
+        if (bad) {
+            if (threadIdx.x == 0) {
+                atomicOr(&d.cnt->flags[FLAG_CAND_BAD], 1u);
+                X[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+                Y[p] = 0.f;
+            }
+            continue;
+        }
         const GroupInfo gi = d.grp[cv.x];
         const uint32_t v = cv.y;
         const double4 mom = d.nd_mom[v];

@@ -154,6 +154,7 @@ __global__ void __launch_bounds__(WALK_TPB, (GEO ? 8 : 1)) k_walk(DevState d) {
     uint32_t *pcb = fb + F;
     uint32_t *ppb = pcb + P;
     const uint32_t ng = d.cnt->n_groups;
+    const uint32_t n_nodes = d.cnt->lvl_off[BH_NLEVELS];
     // geometric walk: the first WALK_LFRONT entries of each frontier live in
     // LDS, the rest at the same index in the wave's global scratch
     uint32_t *la = nullptr, *lb = nullptr;
@@ -200,8 +201,19 @@ __global__ void __launch_bounds__(WALK_TPB, (GEO ? 8 : 1)) k_walk(DevState d) {
         uint32_t ncur = 1, npc = 0, npp = 0;
         unsigned long long pp_particles = 0;
         unsigned long long pp_lane = 0;          // geometric walk: this lane's share, summed once per group
-        bool ovf = false;
-        while (ncur > 0 && !ovf) {
+        bool ovf = false, bound = false;
+        // A walk of a well-formed tree descends one level per frontier and
+        // visits every node at most once; a frontier beyond the deepest level
+        // or more visits than nodes can only come from a malformed tree, and
+        // ends the walk with a flag instead of running on.
+        uint32_t levels = 0;
+        unsigned long long visits = 0;
+        while (ncur > 0 && !ovf && !bound) {
+            visits += ncur;
+            if (++levels > (uint32_t)BH_NLEVELS || visits > (unsigned long long)n_nodes) {
+                bound = true;
+                break;
+            }
             uint32_t nnext = 0;
             for (uint32_t base = 0; base < ncur; base += 64) {
                 const uint32_t k = base + lane;
@@ -266,6 +278,15 @@ __global__ void __launch_bounds__(WALK_TPB, (GEO ? 8 : 1)) k_walk(DevState d) {
             if constexpr (GEO) { t = lcur; lcur = lnxt; lnxt = t; }
             ncur = nnext;
         }
+        if (bound) {
+            if (lane == 0) {
+                atomicOr(&d.cnt->flags[FLAG_WALK_BOUND], 1u);
+                d.g_pc_len[g] = 0;
+                d.g_pp_len[g] = 0;
+                d.g_cost[g] = 0;
+            }
+            continue;
+        }
         if (ovf) {
             if (lane == 0) {
                 atomicOr(&d.cnt->flags[FLAG_WALK_OVF], 1u);
@@ -323,6 +344,8 @@ __global__ void k_walk_reset(DevState d) {
         d.cnt->walk_need_list = 0;
         d.cnt->flags[FLAG_WALK_OVF] = 0;
         d.cnt->flags[FLAG_POOL_OVF] = 0;
+        d.cnt->flags[FLAG_WALK_BOUND] = 0;
+        d.cnt->flags[FLAG_CAND_BAD] = 0;
         d.cnt->cand_used = 0;
     }
 }

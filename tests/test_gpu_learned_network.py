@@ -171,3 +171,54 @@ def test_training_on_a_supplied_set_without_a_tree(torch_cuda):
     _log(f"    mse {mse:.4f}, label variance {Y.var():.4f}")
     assert np.isfinite(mse) and mse < 0.5 * Y.var()
     ctx.close()
+
+
+def _adam_numpy(w0, grads, lr, b1, b2, eps):
+    """Adam as Kingma & Ba (2015) publish it, in FP64: biased first and
+    second moment estimates, their bias corrections by 1 - beta^t, and the
+    step lr * m_hat / (sqrt(v_hat) + eps)."""
+    w = w0.astype(np.float64).copy()
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    for t, g in enumerate(grads, start=1):
+        g = g.astype(np.float64)
+        m = b1 * m + (1.0 - b1) * g
+        v = b2 * v + (1.0 - b2) * g * g
+        m_hat = m / (1.0 - b1 ** t)
+        v_hat = v / (1.0 - b2 ** t)
+        w = w - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return w
+
+
+def test_adam_matches_published_update(torch_cuda):
+    """Ten Adam steps of the library (bh_mlp_adam, the kernel bh_mlp_train
+    applies after each batch) against the published update in numpy, from
+    freshly installed weights (moments and step count start at zero):
+    gradients of mixed signs and scales, some exactly zero; then a second
+    installation restarts the step count."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log("[gpu] adam: 10 steps against the published update")
+    rng = np.random.default_rng(8)
+    X, Y = _synthetic(64, 8)
+    w0 = _weights(X, Y, 8)
+    grads = []
+    for t in range(10):
+        g = (rng.normal(0, 1, 1249) * 10.0 ** rng.uniform(-4, 1, 1249)).astype(np.float32)
+        g[rng.choice(1249, 50, replace=False)] = 0.0
+        grads.append(g)
+    ctx = bh.Context(precision=bh.FP32_REL, criterion=bh.LEARNED)
+    for lr, b1, b2, eps in ((1e-3, 0.9, 0.999, 1e-8), (3e-2, 0.8, 0.99, 1e-6)):
+        ctx.mlp_weights(set=w0)
+        for g in grads:
+            ctx.mlp_adam(torch.as_tensor(g, device="cuda"), lr, b1, b2, eps)
+        torch.cuda.synchronize()
+        got = ctx.mlp_weights()
+        want = _adam_numpy(w0[:1249], grads, lr, b1, b2, eps)
+        err = np.max(np.abs(got[:1249].astype(np.float64) - want))
+        _log(f"    lr={lr} beta=({b1}, {b2}) eps={eps}: max |w_gpu - w_ref| = {err:.2e}")
+        assert err <= 1e-6, err
+        np.testing.assert_array_equal(got[1249:], w0[1249:])     # normalisation untouched
+        moved = np.abs(got[:1249].astype(np.float64) - w0[:1249])
+        assert moved.max() > 5 * lr
+    ctx.close()
