@@ -244,6 +244,22 @@ bh_status bh_step_continue(bh_ctx *ctx, double dt, int32_t n_steps, int32_t rebu
 bh_status bh_direct_sum(bh_ctx *ctx, const bh_system *sys, const int64_t *targets, int64_t n_targets,
                         double *ax, double *ay, double *az, void *stream);
 
+/* bh_direct_sum for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result, bit for bit, with the partial sums
+ * in a static device array of 12 MiB that the library holds on each GPU
+ * until the process ends (its address is looked up once per device by
+ * bh_create) instead of context memory grown on demand.  The call allocates
+ * and frees nothing.  At most BH_DIRECT_STATIC_MAX_TARGETS targets
+ * (BH_EINVAL above that); the context's device must be current (BH_EINVAL
+ * otherwise).  Every call on one GPU shares its array, which keeps the last
+ * call's partial sums (each call writes every partial it reads, so nothing
+ * needs clearing): calls that overlap in time on one GPU, from any context
+ * or stream, race and must be serialised by the caller. */
+#define BH_DIRECT_STATIC_MAX_TARGETS 4096
+bh_status bh_direct_sum_static(bh_ctx *ctx, const bh_system *sys, const int64_t *targets, int64_t n_targets,
+                               double *ax, double *ay, double *az, void *stream);
+
 /* Accelerations of the last force evaluation (bh_forces, bh_step,
  * bh_step_continue) for chosen particles of one system, without copying the
  * rest: for t < n_targets, (ax, ay, az)[t] = acceleration of caller index

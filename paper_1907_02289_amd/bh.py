@@ -26,7 +26,7 @@ SYMBOLS = ("bh_create", "bh_destroy", "bh_set_params", "bh_build_tree", "bh_make
            "bh_step", "bh_step_continue", "bh_direct_sum", "bh_force_timing", "bh_query", "bh_export",
            "bh_export_groups", "bh_stage_times", "bh_autotune", "bh_mlp_collect", "bh_mlp_train",
            "bh_mlp_weights", "bh_mlp_dataset", "bh_mlp_clear", "bh_mlp_set_dataset", "bh_mlp_predict",
-           "bh_mlp_gradient", "bh_mlp_adam", "bh_sample_acc", "bh_last_error")
+           "bh_mlp_gradient", "bh_mlp_adam", "bh_sample_acc", "bh_direct_sum_static", "bh_last_error")
 
 
 class Params(C.Structure):
@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH):
     L.bh_step_continue.argtypes = [vp, dbl, i32, i32, vp]
     L.bh_direct_sum.argtypes = [vp, C.POINTER(System), vp, C.c_int64, vp, vp, vp, vp]
     L.bh_sample_acc.argtypes = [vp, i32, vp, C.c_int64, vp, vp, vp, vp]
+    L.bh_direct_sum_static.argtypes = [vp, C.POINTER(System), vp, C.c_int64, vp, vp, vp, vp]
     L.bh_force_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
     L.bh_autotune.argtypes = [vp, C.POINTER(C.c_int32), i32, i32, C.POINTER(C.c_int32), vp]
     L.bh_mlp_collect.argtypes = [vp, i32, i32, vp]
@@ -225,6 +226,18 @@ class Context:
         self._check(self.L.bh_direct_sum(self.h, arr, C.c_void_p(targets.data_ptr()), nt,
                                          _ptr(out["ax"], nt, "ax"), _ptr(out["ay"], nt, "ay"),
                                          _ptr(out["az"], nt, "az"), _stream()))
+
+    def direct_sum_static(self, system, targets, out):
+        """bh_direct_sum_static: direct_sum without any device allocation
+        (at most 4096 targets)."""
+        import torch
+        if not (targets.is_cuda and targets.dtype == torch.int64 and targets.is_contiguous()):
+            raise TypeError("targets: need a contiguous CUDA int64 tensor")
+        arr = self._systems([system])
+        nt = targets.numel()
+        self._check(self.L.bh_direct_sum_static(self.h, arr, C.c_void_p(targets.data_ptr()), nt,
+                                                _ptr(out["ax"], nt, "ax"), _ptr(out["ay"], nt, "ay"),
+                                                _ptr(out["az"], nt, "az"), _stream()))
 
     def sample_acc(self, targets, out, system=0):
         """Accelerations of the last force evaluation at caller indices

@@ -663,6 +663,11 @@ bh_status bh_create(bh_ctx **out, const bh_params *p) {
         bh_destroy(c);
         return BH_ENOMEM;
     }
+    // the device address of the allocation-free direct sum's static scratch on this GPU
+    if (bhk::direct_static_init(c->device) != hipSuccess) {
+        bh_destroy(c);
+        return BH_EHIP;
+    }
     (void)hipMemset(c->counters.p, 0, sizeof(DevCounters));
     *out = c;
     return BH_OK;
@@ -902,6 +907,31 @@ bh_status bh_direct_sum(bh_ctx *c, const bh_system *sys, const int64_t *targets,
     const bhk::Contact ct{c->P.r_coll, c->P.kappa, c->P.eta, sys->vx, sys->vy, sys->vz};
     bhk::direct_sum(sys->x, sys->y, sys->z, sys->m, sys->n, targets, n_targets, c->P.eps * c->P.eps, c->P.G,
                     coll ? &ct : nullptr, ax, ay, az, P<double>(c->direct_part), (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return BH_OK;
+}
+
+bh_status bh_direct_sum_static(bh_ctx *c, const bh_system *sys, const int64_t *targets, int64_t n_targets,
+                               double *ax, double *ay, double *az, void *stream) {
+    if (!c || !sys) return BH_EINVAL;
+    if (sys->n < 1 || !sys->x || !sys->y || !sys->z || !sys->m || n_targets < 0 || sys->n >= (1ll << 31))
+        return fail(c, BH_EINVAL, "bh_direct_sum_static: bad system or targets");
+    if (n_targets > bhk::direct_static_max_targets())
+        return fail(c, BH_EINVAL, "bh_direct_sum_static: more targets than its static scratch holds (4096)");
+    if (n_targets > 0 && (!targets || !ax || !ay || !az))
+        return fail(c, BH_EINVAL, "bh_direct_sum_static: null target or output array");
+    const bool coll = c->P.r_coll > 0.0;
+    if (coll && (!sys->vx || !sys->vy || !sys->vz))
+        return fail(c, BH_EINVAL, "bh_direct_sum_static: the collision branch needs velocities");
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev != c->device) return fail(c, BH_EINVAL, "bh_direct_sum_static: the context's device must be current");
+    double *part = bhk::direct_static_scratch(dev);
+    if (!part) return fail(c, BH_ESTATE, "bh_direct_sum_static: no static scratch on this device");
+    if (n_targets == 0) return BH_OK;
+    const bhk::Contact ct{c->P.r_coll, c->P.kappa, c->P.eta, sys->vx, sys->vy, sys->vz};
+    bhk::direct_sum(sys->x, sys->y, sys->z, sys->m, sys->n, targets, n_targets, c->P.eps * c->P.eps, c->P.G,
+                    coll ? &ct : nullptr, ax, ay, az, part, (hipStream_t)stream);
     HIPCHK(c, hipGetLastError());
     return BH_OK;
 }

@@ -9,6 +9,8 @@
 // same 64 targets; wave partials are added in a fixed order and written per
 // source chunk, and a second kernel adds the chunks in order.  Gravity
 // (scaled by G at the end) and contact terms are summed separately.
+#include <mutex>
+
 #include "bh_internal.hpp"
 
 namespace {
@@ -16,6 +18,18 @@ namespace {
 constexpr int DT = 256;
 constexpr int DCHUNKS = 64;
 constexpr int NC = 6;   // per (chunk, target): gravity x, y, z, contact x, y, z
+
+// Partial sums of the allocation-free direct sum (bh_direct_sum_static):
+// room for DIRECT_STATIC_MAX_TARGETS targets at the largest chunk count,
+// 12 MiB, one copy on every GPU the library runs on, held until the process
+// ends.  Host code never passes this name to a kernel: it is a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, per device.
+constexpr int64_t DIRECT_STATIC_MAX_TARGETS = 4096;
+static __device__ __align__(256) double scratch[(size_t)DCHUNKS * DIRECT_STATIC_MAX_TARGETS * NC];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double *scratch_dev[MAX_DEVICES] = {};
 
 template <bool COLL>
 __global__ void __launch_bounds__(DT) k_direct_part(const double *x, const double *y, const double *z,
@@ -110,6 +124,29 @@ __global__ void k_direct_sum(const double *part, int64_t nt, int chunks, double 
 }  // namespace
 
 namespace bhk {
+
+int64_t direct_static_max_targets() { return DIRECT_STATIC_MAX_TARGETS; }
+
+hipError_t direct_static_init(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_dev[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;      // the device must be current
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_dev[device] = static_cast<double *>(p);
+    return hipSuccess;
+}
+
+double *direct_static_scratch(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    return scratch_dev[device];
+}
 
 size_t direct_scratch_bytes(int64_t n_targets) {
     return (size_t)DCHUNKS * (size_t)n_targets * NC * sizeof(double);

@@ -252,6 +252,12 @@ struct Contact {
     const double *vx, *vy, *vz;
 };
 size_t direct_scratch_bytes(int64_t n_targets);
+// The allocation-free variant's scratch: a static device array per GPU.
+// direct_static_init (with that device current) looks up its address once;
+// direct_static_scratch returns it (nullptr before the lookup).
+int64_t direct_static_max_targets();
+hipError_t direct_static_init(int device);
+double *direct_static_scratch(int device);
 void direct_sum(const double *x, const double *y, const double *z, const double *m, int64_t n,
                 const int64_t *targets, int64_t nt, double eps2, double G, const Contact *contact, double *ax,
                 double *ay, double *az, double *scratch, hipStream_t s);
