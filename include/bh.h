@@ -119,6 +119,23 @@ typedef struct {
      * library.  BH_EXPORT_ROOT_BOX then holds (-pi, min r, min z,
      * 2^21 / S). */
     double cyl_radius;
+    /* Drift monitor of list-reusing steps (bh_step, bh_step_continue; the
+     * persistent interaction list of Sec. 4.2 keeps lists for several steps,
+     * the paper for a fixed number).  Off when reuse_drift is 0.  On, the
+     * moment refresh of each reusing step also measures how far each node's
+     * particles have moved since the tree was built relative to the node's
+     * centre of mass (leaf: the largest |(x_i - x_i^build) - (c - c^build)|;
+     * a parent: the largest child value plus the child's centre-of-mass
+     * motion relative to the parent's), and the lists are rebuilt before
+     * that step's force evaluation when, at some tree level, the nodes whose
+     * drift exceeds reuse_drift times their side hold more than reuse_frac
+     * of all particles.  rebuild_every then caps the list age.  One host
+     * synchronisation per reusing step.  reuse_drift finite >= 0,
+     * reuse_frac in [0, 1]. */
+    double reuse_drift, reuse_frac;
+    /* Sources per LDS tile of the FP32 gravity-only force kernel: 256 or 512
+     * (0 = 512; other kernels use 512).  bh_autotune sets it. */
+    int32_t force_tile;
 } bh_params;
 
 /* bh_params.flags: replay list-reusing steps eagerly instead of from a HIP graph. */
@@ -153,6 +170,9 @@ typedef struct {
     int64_t interactions_evaluated;  /* running total over every force evaluation of the context */
     int64_t force_evaluations;       /* running count of force evaluations */
     int64_t tree_builds;             /* running count of tree builds */
+    int64_t drift_rebuilds;          /* running count of builds the drift monitor asked for */
+    int64_t host_syncs;              /* running count of host synchronisations on the work stream */
+    int32_t force_tile;              /* sources per LDS tile of the FP32 gravity force kernel in effect */
 } bh_sizes;
 
 /* What bh_export copies out (to HOST memory; the call synchronises `stream`).
@@ -177,7 +197,9 @@ typedef enum {
     BH_EXPORT_NODE_QN = 9,    /* float[n_nodes]: |Q|_F / (M side^2); learned rule only */
     BH_EXPORT_GROUP_EXTRA = 10, /* double[n_groups][2]: half-diagonal of the group's FP64 box and the
                                    mean self-gravity |a| of its particles; learned rule only */
-    BH_EXPORT_ROOT_BOX = 11   /* double[n_systems][4]: root-box lower corner x, y, z and 2^21 / side */
+    BH_EXPORT_ROOT_BOX = 11,  /* double[n_systems][4]: root-box lower corner x, y, z and 2^21 / side */
+    BH_EXPORT_DRIFT = 12      /* double[n_nodes]: drift of each node measured by the last list-reusing
+                                 step's moment refresh (drift monitor only; undefined before one) */
 } bh_what;
 
 /* Create a context.  p is copied.  BH_EINVAL for out-of-range parameters. */
@@ -278,13 +300,15 @@ bh_status bh_sample_acc(bh_ctx *ctx, int32_t sys, const int64_t *targets, int64_
  * reading. */
 bh_status bh_force_timing(bh_ctx *ctx, double *total_ms, int64_t *launches, int32_t reset);
 
-/* Group-size autotuner (the scheduling of Sec. 4.6 leaves the group size
- * free): for each candidate group size, regroup the current tree, walk and
- * evaluate forces once, timing both with HIP events; keep the candidate with
- * the smallest force time + walk time / rebuild_every and leave its lists in
- * place.  Speed at the context's theta only: a larger group is also more
- * accurate at equal theta, which this call does not weigh.  Requires
- * bh_build_tree.  *chosen (may be NULL) receives the group size. */
+/* Group-size and tile autotuner (the scheduling of Sec. 4.6 leaves the
+ * group size free): for each candidate group size, regroup the current tree,
+ * walk and evaluate forces, timing both with HIP events (FP32 without the
+ * collision branch: once per force tile, 512 and 256 sources); keep the pair
+ * with the smallest force time + walk time / rebuild_every, set n_group and
+ * force_tile of the context's parameters to it and leave its lists in place.
+ * Speed at the context's theta only: a larger group is also more accurate
+ * at equal theta, which this call does not weigh.  Requires bh_build_tree.
+ * *chosen (may be NULL) receives the group size; bh_query the tile. */
 bh_status bh_autotune(bh_ctx *ctx, const int32_t *candidates, int32_t n_candidates, int32_t rebuild_every,
                       int32_t *chosen, void *stream);
 

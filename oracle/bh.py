@@ -20,7 +20,7 @@ from . import build as _build
 __all__ = [
     "lib", "keys", "sort_perm", "tree", "moments", "groups", "group_boxes",
     "lists", "forces", "direct", "central", "bh_accel", "direct_accel",
-    "kdk", "n_threads", "BHState", "lg2p", "node_qn", "box_ratio2", "features", "mlp_forward", "lists_learned",
+    "kdk", "node_drift", "n_threads", "BHState", "lg2p", "node_qn", "box_ratio2", "features", "mlp_forward", "lists_learned",
     "label_ratio", "keys_cyl", "atan2", "CYL_PERIOD",
 ]
 
@@ -298,7 +298,8 @@ def direct_accel(x, y, z, m, eps, G=1.0, vel=None, contact=None):
 
 
 def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
-        theta=None, n_leaf=8, n_grp=64, rebuild_every=1, contact=None, trace=None, cyl_r=0.0):
+        theta=None, n_leaf=8, n_grp=64, rebuild_every=1, contact=None, trace=None, cyl_r=0.0,
+        rebuild_at=None):
     """Kick-drift-kick leapfrog in FP64 (the integration step (4) of Sec. 4.2).
 
     theta=None uses the direct sum; otherwise Barnes-Hut with lists rebuilt
@@ -307,8 +308,11 @@ def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
     dashpot sees the velocities held when the force is evaluated: the
     initial ones for the first evaluation, the half-kicked ones after each
     drift.  cyl_r > 0 builds the trees on cylindrical coordinates around
-    that radius.  trace, if given, is called as trace(step, x, y, z, vx, vy, vz)
-    after every completed step.  Returns new copies of (x, y, z, vx, vy, vz).
+    that radius.  rebuild_at, if given, replaces rebuild_every: the set of
+    force evaluations (0 = the first, k = the one ending step k) before which
+    the tree and lists are built.  trace, if given, is called as
+    trace(step, x, y, z, vx, vy, vz) after every completed step.  Returns new
+    copies of (x, y, z, vx, vy, vz).
     """
     x, y, z, vx, vy, vz = (np.array(a, dtype=np.float64, copy=True) for a in (x, y, z, vx, vy, vz))
     m = _f64(m)
@@ -320,7 +324,8 @@ def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
         if theta is None:
             ax, ay, az, _ = direct(x, y, z, m, eps, G, vel=vel, contact=contact)
         else:
-            if state is None or step % rebuild_every == 0:
+            build = step % rebuild_every == 0 if rebuild_at is None else step in rebuild_at
+            if state is None or build:
                 state = BHState(x, y, z, m, theta, n_leaf, n_grp, cyl_r=cyl_r)
             else:
                 state.refresh(x, y, z, m)
@@ -345,6 +350,38 @@ def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
         if trace is not None:
             trace(k, x, y, z, vx, vy, vz)
     return x, y, z, vx, vy, vz
+
+
+def node_drift(t, x_build, x_now, com_build, com_now):
+    """Drift of every tree node since the build (the rebuild monitor of
+    list-reusing steps; the paper reuses lists for a fixed number of steps,
+    Sec. 4.2, this measures when the moved particles have left the build's
+    geometry).  For a leaf: the largest distance by which one of its
+    particles has moved relative to the leaf's centre of mass,
+        max_i |(x_i - x_i^build) - (c - c^build)|;
+    for a parent: the largest over its children of the child's drift plus
+    the child's centre-of-mass motion relative to the parent's, a bound of
+    the leaf form over the parent's particles.  x_*: (n, 3) positions in the
+    tree's order; com_*: (n_nodes, 3) centres of mass.  Returns
+    (drift, direct): direct is the leaf form over each node's particles."""
+    x_build = np.asarray(x_build, np.float64)
+    x_now = np.asarray(x_now, np.float64)
+    dc = np.asarray(com_now, np.float64) - np.asarray(com_build, np.float64)
+    nn = t["begin"].size
+    drift = np.zeros(nn)
+    direct = np.zeros(nn)
+    for v in range(nn - 1, -1, -1):          # children have larger ids than their parents
+        b, c = int(t["begin"][v]), int(t["count"][v])
+        e = (x_now[b:b + c] - x_build[b:b + c]) - dc[v]
+        direct[v] = np.sqrt(e[:, 0] * e[:, 0] + e[:, 1] * e[:, 1] + e[:, 2] * e[:, 2]).max()
+        if t["n_child"][v] == 0:
+            drift[v] = direct[v]
+        else:
+            f = int(t["first_child"][v])
+            ch = np.arange(f, f + int(t["n_child"][v]))
+            q = dc[ch] - dc[v]
+            drift[v] = (drift[ch] + np.sqrt(q[:, 0] * q[:, 0] + q[:, 1] * q[:, 1] + q[:, 2] * q[:, 2])).max()
+    return drift, direct
 
 
 # ---------------------------------------------------------------------------

@@ -18,7 +18,7 @@ FP64, FP32_REL = 0, 1
 FLAG_NO_GRAPH = 1
 GEOMETRIC, LEARNED = 0, 1
 EXPORT = dict(keys=0, perm=1, nodes=2, moments=3, groups=4, lists=5, acc_sorted=6, sorted_pos=7, quad=8,
-              node_qn=9, group_extra=10, root_box=11)
+              node_qn=9, group_extra=10, root_box=11, drift=12)
 MLP_NPARAM = 1259
 STAGES = ("keys_sort", "tree", "moments", "groups", "walk", "forces", "integrate", "step")
 
@@ -34,7 +34,8 @@ class Params(C.Structure):
                 ("n_leaf", C.c_int32), ("n_group", C.c_int32), ("precision", C.c_int32),
                 ("criterion", C.c_int32), ("theta_min", C.c_double), ("theta_max", C.c_double),
                 ("tau", C.c_double), ("flags", C.c_int32), ("r_coll", C.c_double), ("kappa", C.c_double),
-                ("eta", C.c_double), ("cyl_radius", C.c_double)]
+                ("eta", C.c_double), ("cyl_radius", C.c_double), ("reuse_drift", C.c_double),
+                ("reuse_frac", C.c_double), ("force_tile", C.c_int32)]
 
 
 class System(C.Structure):
@@ -55,7 +56,8 @@ class Sizes(C.Structure):
                 ("n_nodes", C.c_int64), ("n_groups", C.c_int64), ("n_pc", C.c_int64), ("n_pp", C.c_int64),
                 ("interactions", C.c_int64), ("n_group_used", C.c_int32), ("lists_valid", C.c_int32),
                 ("interactions_evaluated", C.c_int64), ("force_evaluations", C.c_int64),
-                ("tree_builds", C.c_int64)]
+                ("tree_builds", C.c_int64), ("drift_rebuilds", C.c_int64), ("host_syncs", C.c_int64),
+                ("force_tile", C.c_int32)]
 
 
 _lib = None
@@ -81,8 +83,8 @@ def load_library(path: str = LIB_PATH):
     L.bh_step.argtypes = [vp, C.POINTER(System), i32, dbl, i32, i32, vp]
     L.bh_step_continue.argtypes = [vp, dbl, i32, i32, vp]
     L.bh_direct_sum.argtypes = [vp, C.POINTER(System), vp, C.c_int64, vp, vp, vp, vp]
-    L.bh_sample_acc.argtypes = [vp, i32, vp, C.c_int64, vp, vp, vp, vp]
     L.bh_direct_sum_static.argtypes = [vp, C.POINTER(System), vp, C.c_int64, vp, vp, vp, vp]
+    L.bh_sample_acc.argtypes = [vp, i32, vp, C.c_int64, vp, vp, vp, vp]
     L.bh_force_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
     L.bh_autotune.argtypes = [vp, C.POINTER(C.c_int32), i32, i32, C.POINTER(C.c_int32), vp]
     L.bh_mlp_collect.argtypes = [vp, i32, i32, vp]
@@ -136,11 +138,12 @@ class Context:
 
     def __init__(self, theta=0.5, eps=1e-3, G=1.0, central_mass=0.0, n_leaf=8, n_group=64,
                  precision=FP64, criterion=GEOMETRIC, theta_min=0.2, theta_max=1.0, tau=1e-3,
-                 use_graphs=True, r_coll=0.0, kappa=0.0, eta=0.0, cyl_radius=0.0):
+                 use_graphs=True, r_coll=0.0, kappa=0.0, eta=0.0, cyl_radius=0.0, reuse_drift=0.0,
+                 reuse_frac=0.0, force_tile=0):
         self.L = load_library()
         self.params = Params(theta, eps, G, central_mass, n_leaf, n_group, precision, criterion,
                              theta_min, theta_max, tau, 0 if use_graphs else FLAG_NO_GRAPH, r_coll, kappa, eta,
-                             cyl_radius)
+                             cyl_radius, reuse_drift, reuse_frac, force_tile)
         h = C.c_void_p()
         self._check(self.L.bh_create(C.byref(h), C.byref(self.params)), ctx=None)
         self.h = h
@@ -252,9 +255,13 @@ class Context:
                                          _ptr(out["az"], nt, "az"), _stream()))
 
     def autotune(self, candidates=(64, 128, 256, 512), rebuild_every=4):
+        """Group size (returned) and force tile (then in query()["force_tile"])
+        by measured time; the context's parameters take both."""
         arr = (C.c_int32 * len(candidates))(*candidates)
         out = C.c_int32()
         self._check(self.L.bh_autotune(self.h, arr, len(candidates), int(rebuild_every), C.byref(out), _stream()))
+        self.params.n_group = out.value
+        self.params.force_tile = self.query()["force_tile"]
         return out.value
 
     # ---- learned opening rule
@@ -364,6 +371,8 @@ class Context:
             out = np.zeros((ng, 4), np.int64)
         elif what in ("acc_sorted", "sorted_pos"):
             out = np.zeros((n, 4))
+        elif what == "drift":
+            out = np.zeros(nn)
         elif what == "quad":
             out = np.zeros((nn, 6))
         elif what == "node_qn":

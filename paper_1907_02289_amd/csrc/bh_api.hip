@@ -62,6 +62,7 @@ struct bh_ctx {
     DevBuf gmark, grp, g_lo, g_hi, g_cen, g_pc_off, g_pc_len, g_pp_off, g_pp_len, g_cost, order;
     DevBuf gkey_a, gkey_b, gval_a, gval_b;
     DevBuf pc_pool, pp_pool, walk_scratch, counters;
+    DevBuf pos_b, nd_mom_b, nd_drift;    // drift monitor: build snapshot and per-node drift
 
     // pinned host staging
     DevCounters *h_cnt = nullptr;
@@ -77,6 +78,7 @@ struct bh_ctx {
 
     // running totals and integration state
     int64_t interactions_evaluated = 0, force_evaluations = 0, tree_builds = 0;
+    int64_t drift_rebuilds = 0, host_syncs = 0;
     bool state_valid = false;     // sorted x, v, a ready for bh_step_continue
     bool have_vel = false;
     int age = 0;                  // force evaluations done with the current lists
@@ -241,6 +243,12 @@ void refresh_state(bh_ctx *c) {
     d.kappa = c->P.kappa;
     d.eta = c->P.eta;
     d.cyl_r = c->P.cyl_radius;
+    const bool monitor = c->P.reuse_drift > 0.0;
+    d.pos_b = monitor ? P<double4>(c->pos_b) : nullptr;
+    d.nd_mom_b = monitor ? P<double4>(c->nd_mom_b) : nullptr;
+    d.nd_drift = nullptr;     // set only for the monitored moment pass of a list-reusing step
+    d.drift_kappa = c->P.reuse_drift;
+    d.force_tile = c->P.force_tile == 256 ? 256 : 512;
 }
 
 bh_status check_params(const bh_params *p) {
@@ -260,6 +268,9 @@ bh_status check_params(const bh_params *p) {
     if (p->criterion == BH_OPEN_LEARNED)
         for (double v : {p->theta_min, p->theta_max, p->tau})
             if (!(v >= 0.0) || !std::isfinite(v)) return BH_EINVAL;
+    if (!(p->reuse_drift >= 0.0) || !std::isfinite(p->reuse_drift)) return BH_EINVAL;
+    if (!(p->reuse_frac >= 0.0) || !(p->reuse_frac <= 1.0)) return BH_EINVAL;
+    if (p->force_tile != 0 && p->force_tile != 256 && p->force_tile != 512) return BH_EINVAL;
     return BH_OK;
 }
 
@@ -282,6 +293,18 @@ bh_status wait_tables(bh_ctx *c) {
 bh_status read_counters(bh_ctx *c, hipStream_t s) {
     HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->counters.p, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
+    c->host_syncs += 1;
+    return BH_OK;
+}
+
+// Build snapshot and drift buffers of the drift monitor (only when it is on).
+bh_status ensure_drift(bh_ctx *c) {
+    if (!(c->P.reuse_drift > 0.0)) return BH_OK;
+    if (c->n_cap) HIPCHK(c, grow(c->pos_b, (size_t)c->n_cap * sizeof(double4)));
+    if (c->node_cap) {
+        HIPCHK(c, grow(c->nd_mom_b, (size_t)c->node_cap * sizeof(double4)));
+        HIPCHK(c, grow(c->nd_drift, (size_t)c->node_cap * sizeof(double)));
+    }
     return BH_OK;
 }
 
@@ -338,6 +361,7 @@ bh_status ensure_particles(bh_ctx *c, uint32_t n) {
     HIPCHK(c, grow(c->gval_a, u4));
     HIPCHK(c, grow(c->gval_b, u4));
     c->n_cap = cap;
+    STCHK(ensure_drift(c));
     if (c->P.criterion == BH_OPEN_LEARNED) {
         HIPCHK(c, grow(c->amag, u8));
         HIPCHK(c, grow(c->amag_in, u8));
@@ -382,6 +406,7 @@ bh_status ensure_nodes(bh_ctx *c, uint32_t cap) {
     HIPCHK(c, grow(c->tmp_a, (size_t)cap * 4));
     HIPCHK(c, grow(c->tmp_b, (size_t)cap * 4));
     c->node_cap = cap;
+    STCHK(ensure_drift(c));
     return BH_OK;
 }
 
@@ -462,6 +487,8 @@ bh_status rebuild(bh_ctx *c, hipStream_t s, bool from_caller) {
     ev_end(c, EV_GROUPS, s);
     STCHK(read_counters(c, s));
     c->n_groups = c->h_cnt->n_groups;
+    // the drift monitor measures motion from here
+    if (c->P.reuse_drift > 0.0) bhk::drift_snapshot(c->d, s);
     c->tree_valid = true;
     c->lists_valid = false;
     c->tree_builds += 1;
@@ -554,8 +581,11 @@ bh_status make_lists(bh_ctx *c, hipStream_t s) {
 }
 
 // Persistent workgroups of the force kernel: as many as stay resident (FP32:
-// 6 per CU by its register cap; FP64: 4 at its register use).
-int force_blocks(const bh_ctx *c) { return c->n_cu * (c->P.precision == BH_FP32_REL ? 6 : 4); }
+// 6 per CU by its register cap; FP64: 5 by its cap, 3 with the collision branch).
+int force_blocks(const bh_ctx *c) {
+    if (c->P.precision == BH_FP32_REL) return c->n_cu * 6;
+    return c->n_cu * (c->P.r_coll > 0.0 ? 3 : 5);
+}
 
 // kick_h != 0: the launch also applies the closing half kick v += kick_h a.
 // The kernels with the collision branch ignore it, so callers pass it only
@@ -685,7 +715,7 @@ bh_status bh_destroy(bh_ctx *c) {
                      &c->gval_b, &c->pc_pool, &c->pp_pool, &c->walk_scratch, &c->counters, &c->direct_part,
                      &c->nd_qn, &c->amag, &c->amag_in, &c->g_amin, &c->g_rad, &c->cand, &c->mlp_w, &c->mlp_m,
                      &c->mlp_v, &c->mlp_g, &c->act, &c->ds_x, &c->ds_y, &c->ds_pairs, &c->pk_a, &c->pk_b,
-                     &c->pv_a, &c->pv_b, &c->phist, &c->eval_out};
+                     &c->pv_a, &c->pv_b, &c->phist, &c->eval_out, &c->pos_b, &c->nd_mom_b, &c->nd_drift};
     for (DevBuf *b : all) release(*b);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
     if (c->h_systab) (void)hipHostFree(c->h_systab);
@@ -717,10 +747,13 @@ bh_status bh_set_params(bh_ctx *c, const bh_params *p) {
     if (ng != c->n_grp_used || p->n_leaf != c->P.n_leaf || p->criterion != c->P.criterion ||
         p->cyl_radius != c->P.cyl_radius)
         c->tree_valid = false;
+    // switching the drift monitor on needs a build snapshot: the tree is rebuilt first
+    if (p->reuse_drift > 0.0 && !(c->P.reuse_drift > 0.0)) c->tree_valid = false;
     c->P = *p;
     c->n_grp_used = ng;
     c->lists_valid = false;
     STCHK(ensure_learned(c));
+    STCHK(ensure_drift(c));
     return BH_OK;
 }
 
@@ -780,11 +813,13 @@ bool same_key(const bh_ctx::GraphEntry &g, const DevState &d, double h, double d
     return g.exec && g.h == h && g.dt == dt && std::memcmp(&g.key, &d, sizeof(DevState)) == 0;
 }
 
-// Kick-drift and moment refresh of a list-reusing step, from a cached graph.
-bh_status reuse_prefix_graph(bh_ctx *c, double h, double dt, hipStream_t s) {
+// Kick-drift and moment refresh of a list-reusing step, from a cached graph
+// (with the drift monitor on, dd carries its buffers: the counts are cleared
+// by a kernel inside the graph and the moment pass measures the drift).
+bh_status reuse_prefix_graph(bh_ctx *c, const DevState &dd, double h, double dt, hipStream_t s) {
     bh_ctx::GraphEntry *hit = nullptr;
     for (auto &g : c->graphs)
-        if (same_key(g, c->d, h, dt)) hit = &g;
+        if (same_key(g, dd, h, dt)) hit = &g;
     if (!hit) {
         hit = &c->graphs[c->graph_next];
         c->graph_next ^= 1;
@@ -794,13 +829,14 @@ bh_status reuse_prefix_graph(bh_ctx *c, double h, double dt, hipStream_t s) {
         }
         hipGraph_t graph = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->gs, hipStreamCaptureModeThreadLocal));
-        bhk::kick_drift(c->d, h, dt, c->gs);
-        bhk::moments(c->d, c->gs);
+        bhk::kick_drift(dd, h, dt, c->gs);
+        if (dd.nd_drift) bhk::drift_clear(dd, c->gs);
+        bhk::moments(dd, c->gs);
         HIPCHK(c, hipStreamEndCapture(c->gs, &graph));
         hipError_t e = hipGraphInstantiate(&hit->exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIPCHK(c, e);
-        std::memcpy(&hit->key, &c->d, sizeof(DevState));
+        std::memcpy(&hit->key, &dd, sizeof(DevState));
         hit->h = h;
         hit->dt = dt;
         c->graph_captures += 1;
@@ -817,6 +853,7 @@ bh_status reuse_prefix_graph(bh_ctx *c, double h, double dt, hipStream_t s) {
 bh_status integrate(bh_ctx *c, double dt, int32_t n_steps, int32_t rebuild_every, hipStream_t s) {
     const double h = 0.5 * dt;
     const bool graphs = !(c->P.flags & BH_FLAG_NO_GRAPH);
+    const bool monitor = c->P.reuse_drift > 0.0;
     for (int k = 0; k < n_steps; ++k) {
         if (c->age >= rebuild_every) {
             ev_begin(c, EV_INTEG, s);
@@ -824,16 +861,36 @@ bh_status integrate(bh_ctx *c, double dt, int32_t n_steps, int32_t rebuild_every
             ev_end(c, EV_INTEG, s);
             STCHK(rebuild(c, s, false));
             STCHK(make_lists(c, s));
-        } else if (graphs) {
-            refresh_state(c);
-            STCHK(reuse_prefix_graph(c, h, dt, s));
         } else {
-            ev_begin(c, EV_INTEG, s);
-            bhk::kick_drift(c->d, h, dt, s);
-            ev_end(c, EV_INTEG, s);
-            ev_begin(c, EV_MOM, s);
-            bhk::moments(c->d, s);
-            ev_end(c, EV_MOM, s);
+            refresh_state(c);
+            DevState dd = c->d;
+            if (monitor) dd.nd_drift = P<double>(c->nd_drift);
+            if (graphs) {
+                STCHK(reuse_prefix_graph(c, dd, h, dt, s));
+            } else {
+                ev_begin(c, EV_INTEG, s);
+                bhk::kick_drift(dd, h, dt, s);
+                ev_end(c, EV_INTEG, s);
+                ev_begin(c, EV_MOM, s);
+                if (monitor) bhk::drift_clear(dd, s);
+                bhk::moments(dd, s);
+                ev_end(c, EV_MOM, s);
+            }
+            if (monitor) {
+                // Drift monitor: the lists are rebuilt before this force
+                // evaluation when, at some tree level, the nodes whose particles
+                // moved by more than reuse_drift times the node's side relative to
+                // its centre of mass since the build hold more than reuse_frac of
+                // the particles.
+                STCHK(read_counters(c, s));
+                uint32_t most = 0;
+                for (int l = 0; l < BH_NLEVELS; ++l) most = std::max(most, c->h_cnt->stale[l]);
+                if ((double)most > c->P.reuse_frac * (double)c->n) {
+                    STCHK(rebuild(c, s, false));
+                    STCHK(make_lists(c, s));
+                    c->drift_rebuilds += 1;
+                }
+            }
         }
         refresh_state(c);
         // the closing kick rides in the force launch unless the collision
@@ -973,7 +1030,11 @@ bh_status bh_autotune(bh_ctx *c, const int32_t *cand, int32_t n_cand, int32_t re
         if (cand[k] < 1 || cand[k] > 65536) return fail(c, BH_EINVAL, "bh_autotune: bad group size");
     hipStream_t s = (hipStream_t)stream;
     double best = 1e300;
-    int best_g = cand[0];
+    int best_g = cand[0], best_tile = c->P.force_tile;
+    // the force kernel's tile (sources per LDS tile) is tried for each group
+    // size where there is a choice: the FP32 gravity-only kernels
+    std::vector<int> tiles{c->P.force_tile == 256 ? 256 : 512};
+    if (c->P.precision == BH_FP32_REL && !(c->P.r_coll > 0.0)) tiles = {512, 256};
     for (int pass = 0; pass < 2; ++pass) {
         for (int k = 0; k < (pass == 0 ? n_cand : 1); ++k) {
             c->n_grp_used = pass == 0 ? cand[k] : best_g;
@@ -983,19 +1044,31 @@ bh_status bh_autotune(bh_ctx *c, const int32_t *cand, int32_t n_cand, int32_t re
             STCHK(read_counters(c, s));
             c->n_groups = c->h_cnt->n_groups;
             STCHK(make_lists(c, s));
-            refresh_state(c);
-            STCHK(run_forces(c, s, false));
-            if (pass == 1) break;
+            if (pass == 1) {
+                c->P.force_tile = best_tile;
+                refresh_state(c);
+                STCHK(run_forces(c, s, false));
+                break;
+            }
             double ms[EV_N];
             STCHK(bh_stage_times(c, ms));
-            const double t = ms[EV_FORCE] + ms[EV_WALK] / rebuild_every;
-            if (t < best) {
-                best = t;
-                best_g = cand[k];
+            const double walk_ms = ms[EV_WALK];
+            for (int tile : tiles) {
+                c->P.force_tile = tile;
+                refresh_state(c);
+                STCHK(run_forces(c, s, false));
+                STCHK(bh_stage_times(c, ms));
+                const double t = ms[EV_FORCE] + walk_ms / rebuild_every;
+                if (t < best) {
+                    best = t;
+                    best_g = cand[k];
+                    best_tile = tile;
+                }
             }
         }
     }
     c->P.n_group = best_g;
+    c->P.force_tile = best_tile;
     c->state_valid = false;
     if (chosen) *chosen = best_g;
     return BH_OK;
@@ -1260,6 +1333,9 @@ bh_status bh_query(const bh_ctx *c, bh_sizes *o) {
     o->interactions_evaluated = c->interactions_evaluated;
     o->force_evaluations = c->force_evaluations;
     o->tree_builds = c->tree_builds;
+    o->drift_rebuilds = c->drift_rebuilds;
+    o->host_syncs = c->host_syncs;
+    o->force_tile = c->P.force_tile == 256 ? 256 : 512;
     return BH_OK;
 }
 
@@ -1374,6 +1450,10 @@ bh_status bh_export(bh_ctx *c, int32_t what, void *dst, void *stream) {
         }
         return BH_OK;
     }
+    case BH_EXPORT_DRIFT:
+        if (!c->tree_valid || !(c->P.reuse_drift > 0.0)) return fail(c, BH_ESTATE, "no drift monitor");
+        HIPCHK(c, hipMemcpy(dst, c->nd_drift.p, nn * sizeof(double), hipMemcpyDeviceToHost));
+        return BH_OK;
     case BH_EXPORT_ROOT_BOX:
         if (!c->tree_valid) return fail(c, BH_ESTATE, "no tree");
         HIPCHK(c, hipMemcpy(dst, c->box_b.p, (size_t)c->n_sys * sizeof(double4), hipMemcpyDeviceToHost));

@@ -14,8 +14,9 @@
 // the particle-pair loop with unit masses and its node masses in units of
 // m0, the sums being scaled by G m0 at the end: one multiply fewer per pair.
 //
-// Sources are staged 512 at a time in LDS as group-relative float4 (x, y,
-// z, m); particle-list leaves are read 256 at a time, a prefix sum over their
+// Sources are staged 512 at a time (the FP32 gravity-only kernels also come
+// with tiles of 256, a choice of the autotuner) in LDS as group-relative
+// float4 (x, y, z, m); particle-list leaves are read 256 at a time, a prefix sum over their
 // sizes places their particles in the tiles, and the FP32 gravity-only
 // kernels list the chunk's particle ids in LDS once so that staging a source
 // is one LDS read (a chunk of more than 2048 particles, possible only with
@@ -56,7 +57,7 @@
 namespace {
 
 constexpr int FT = 256;      // threads per workgroup (4 waves)
-constexpr int TJ = 512;      // sources per LDS tile (two per thread)
+constexpr int TJ_MAX = 512;  // sources per LDS tile at most (two per thread); 256 is the other tile
 constexpr int LC = FT;       // particle-list leaves per chunk (one per thread)
 constexpr int PIDX = 2048;   // particle ids of a leaf chunk listed in LDS (FP32 gravity-only kernels)
 
@@ -77,8 +78,16 @@ template <typename R>
 __device__ __forceinline__ R rsqrt_r(R x);
 template <>
 __device__ __forceinline__ float rsqrt_r<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+// FP64: the hardware estimate (relative error below 2^-24 on gfx950, measured
+// over 1e-20..1e20) refined by one Newton step for y = x^(-1/2),
+// y <- y + (y/2)(1 - x y^2), which squares the error (below 5e-15 measured):
+// far inside the FP64 bar, at a fraction of a division and a square root.
 template <>
-__device__ __forceinline__ double rsqrt_r<double>(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ double rsqrt_r<double>(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
 
 template <typename R>
 __device__ __forceinline__ R fma_r(R a, R b, R c);
@@ -213,17 +222,20 @@ __device__ __forceinline__ void contact_pass(const typename V4<R>::T *tile, cons
 // pair loop needs the occupancy to hide LDS and rsqrt latency (measured:
 // 100 VGPRs / 4 waves per SIMD ran 18% slower; the collision variant, at
 // 5 workgroups without spills, ran 3% slower than at 6 with a few).  FP64
-// keeps the default.
+// gravity-only: 5 workgroups (<= 96 VGPRs, no spills); the FP64 collision
+// variant keeps the default.
 template <typename R, bool COLL>
 struct ForceOcc {
-    static constexpr int blocks = sizeof(R) == 4 ? 6 : 1;
+    static constexpr int blocks = sizeof(R) == 4 ? 6 : (COLL ? 1 : 5);
 };
 
-template <typename R, bool POT, bool ZERO_EPS, bool COLL>
+template <typename R, bool POT, bool ZERO_EPS, bool COLL, int TJ>
 // kick_h != 0: also apply the closing half kick v += kick_h a of a
 // leapfrog step to each particle, as a separate pass over v and a would (the
 // collision branch reads other particles' velocities, so it never fuses).
+// TJ: sources per LDS tile (512, or 256 in the FP32 gravity-only kernels).
 __global__ void __launch_bounds__(FT, (ForceOcc<R, COLL>::blocks)) k_force(DevState d, uint32_t ng, double kick_h) {
+    static_assert(TJ == 256 || TJ == TJ_MAX, "tile of 256 or 512 sources");
     using T4 = typename V4<R>::T;
     __shared__ T4 tile[TJ + 16];
     __shared__ uint32_t lbeg[LC];
@@ -577,17 +589,28 @@ __global__ void k_force_reset(DevState d) {
     if (threadIdx.x == 0 && blockIdx.x == 0) d.cnt->work_counter2 = 0;
 }
 
+template <typename R, bool POT, bool ZERO_EPS>
+void launch_gravity(const DevState &d, uint32_t ng, int blocks, double kick_h, hipStream_t s) {
+    if constexpr (sizeof(R) == 4) {
+        if (d.force_tile == 256) {
+            k_force<R, POT, ZERO_EPS, false, 256><<<blocks, FT, 0, s>>>(d, ng, kick_h);
+            return;
+        }
+    }
+    k_force<R, POT, ZERO_EPS, false, TJ_MAX><<<blocks, FT, 0, s>>>(d, ng, kick_h);
+}
+
 template <typename R, bool POT>
 void launch(const DevState &d, uint32_t ng, int blocks, double kick_h, hipStream_t s) {
     if (d.rc > 0.0) {
         if (d.eps2 == 0.0)
-            k_force<R, POT, true, true><<<blocks, FT, 0, s>>>(d, ng, 0.0);
+            k_force<R, POT, true, true, TJ_MAX><<<blocks, FT, 0, s>>>(d, ng, 0.0);
         else
-            k_force<R, POT, false, true><<<blocks, FT, 0, s>>>(d, ng, 0.0);
+            k_force<R, POT, false, true, TJ_MAX><<<blocks, FT, 0, s>>>(d, ng, 0.0);
     } else if (d.eps2 == 0.0) {
-        k_force<R, POT, true, false><<<blocks, FT, 0, s>>>(d, ng, kick_h);
+        launch_gravity<R, POT, true>(d, ng, blocks, kick_h, s);
     } else {
-        k_force<R, POT, false, false><<<blocks, FT, 0, s>>>(d, ng, kick_h);
+        launch_gravity<R, POT, false>(d, ng, blocks, kick_h, s);
     }
 }
 

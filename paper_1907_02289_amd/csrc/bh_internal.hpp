@@ -38,6 +38,7 @@ struct DevCounters {
     unsigned long long cand_used;       // learned rule: candidate pairs recorded (may exceed capacity)
     uint32_t work_counter3;
     uint32_t pad2;
+    uint32_t stale[BH_NLEVELS];         // drift monitor: particles in drifted nodes, per level
 };
 
 // ---------------------------------------------------------------- wave helpers
@@ -190,6 +191,11 @@ struct DevState {
     double eps2, G, central_mass;
     double rc, kappa, eta;         // collision branch of Eq. (2); rc = 0: off
     double cyl_r;                  // tree on cylindrical coordinates around this radius; 0: Cartesian
+    // drift monitor of list-reusing steps (off when nd_drift is null)
+    double4 *pos_b, *nd_mom_b;     // sorted positions and node moments at the last tree build
+    double *nd_drift;              // [node_cap] drift of each node since the build
+    double drift_kappa;            // a node has drifted when its drift exceeds drift_kappa * side
+    int force_tile;                // sources per LDS tile of the FP32 gravity force kernel: 256 or 512
 };
 
 enum { WALK_GEOMETRIC = 0, WALK_LEARNED = 1, WALK_ENUMERATE = 2 };
@@ -208,6 +214,10 @@ void permute(const DevState &d, hipStream_t s);
 void build_octree(const DevState &d, hipStream_t s);
 void moments(const DevState &d, hipStream_t s);
 void make_groups(const DevState &d, hipStream_t s);
+// drift monitor: keep the build's positions and moments (after a build) and
+// clear the per-level counts (before each monitored moment pass)
+void drift_snapshot(const DevState &d, hipStream_t s);
+void drift_clear(const DevState &d, hipStream_t s);
 void reset_flags(const DevState &d, hipStream_t s);
 void regroup(const DevState &d, hipStream_t s);   // group flags for d.n_grp on the current tree
 

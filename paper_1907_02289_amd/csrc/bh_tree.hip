@@ -373,6 +373,35 @@ __global__ void k_moments_level(DevState d, int l) {
         }
         double4 r = make_double4(sx / M, sy / M, sz / M, M);
         d.nd_mom[v] = r;
+        if (d.nd_drift) {
+            // Drift since the build: the largest distance by which a particle of
+            // the node has moved relative to the node's centre of mass,
+            //   leaf:     max_i |(x_i - x_i^b) - (c - c^b)|,
+            //   internal: max_k (drift_k + |(c_k - c_k^b) - (c - c^b)|),
+            // an upper bound of the leaf form over the node's particles.
+            const double4 rb = d.nd_mom_b[v];
+            const double ux = r.x - rb.x, uy = r.y - rb.y, uz = r.z - rb.z;
+            double dr = 0.0;
+            if (nch == 0) {
+                uint32_t b = d.nd_begin[v], e = b + d.nd_count[v];
+                for (uint32_t i = b; i < e; ++i) {
+                    const double4 p = d.pos[i], q = d.pos_b[i];
+                    const double ex = (p.x - q.x) - ux, ey = (p.y - q.y) - uy, ez = (p.z - q.z) - uz;
+                    dr = fmax(dr, sqrt(ex * ex + ey * ey + ez * ez));
+                }
+            } else {
+                uint32_t f = d.nd_first[v];
+                for (uint32_t c = 0; c < nch; ++c) {
+                    const double4 q = d.nd_mom[f + c], qb = d.nd_mom_b[f + c];
+                    const double ex = (q.x - qb.x) - ux, ey = (q.y - qb.y) - uy, ez = (q.z - qb.z) - uz;
+                    dr = fmax(dr, d.nd_drift[f + c] + sqrt(ex * ex + ey * ey + ez * ez));
+                }
+            }
+            d.nd_drift[v] = dr;
+            const uint32_t meta = d.nd_meta[v];
+            const double side = ldexp((double)(1u << BH_MAXLEVEL) / d.box[meta_sys(meta)].w, -l);
+            if (dr > d.drift_kappa * side) atomicAdd(&d.cnt->stale[l], d.nd_count[v]);
+        }
         if (d.nd_quad) {
             double Q[6] = {0, 0, 0, 0, 0, 0};
             if (nch == 0) {
@@ -528,6 +557,27 @@ void build_octree(const DevState &d, hipStream_t s) {
 void moments(const DevState &d, hipStream_t s) {
     const unsigned g = grid_for(d.node_cap, 4096);
     for (int l = BH_MAXLEVEL; l >= 0; --l) k_moments_level<<<g, TPB, 0, s>>>(d, l);
+}
+
+__global__ void k_drift_snapshot(DevState d) {
+    const uint32_t nn = d.cnt->lvl_off[BH_NLEVELS];
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t t0 = blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t i = t0; i < d.n; i += stride) d.pos_b[i] = d.pos[i];
+    for (uint32_t v = t0; v < nn; v += stride) d.nd_mom_b[v] = d.nd_mom[v];
+    if (t0 < BH_NLEVELS) d.cnt->stale[t0] = 0;
+}
+
+__global__ void k_drift_clear(DevState d) {
+    if (threadIdx.x < BH_NLEVELS) d.cnt->stale[threadIdx.x] = 0;
+}
+
+void drift_snapshot(const DevState &d, hipStream_t s) {
+    k_drift_snapshot<<<grid_for(d.n, 4096), TPB, 0, s>>>(d);
+}
+
+void drift_clear(const DevState &d, hipStream_t s) {
+    k_drift_clear<<<1, 64, 0, s>>>(d);
 }
 
 void regroup(const DevState &d, hipStream_t s) {

@@ -99,3 +99,31 @@ def test_binding_checks_a_supplied_training_set():
         ctx.mlp_set_dataset(np.zeros((5, 4)), np.zeros(4))
     with pytest.raises(ValueError):
         ctx.mlp_set_dataset(np.zeros((5, 4)), np.zeros(5), pairs=np.zeros((4, 2)))
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of bh_params, bh_sizes and bh_train_opts have the C
+    layout: sizes and every field offset as a C compiler lays them out from
+    include/bh.h."""
+    import ctypes
+    import subprocess
+    from paper_1907_02289_amd import bh
+    structs = {"bh_params": bh.Params, "bh_sizes": bh.Sizes, "bh_train_opts": bh.TrainOpts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bh.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, f, v = line.split()
+        got[(cname, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

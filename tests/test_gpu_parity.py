@@ -180,6 +180,34 @@ def test_fp32_relative_forces(torch_cuda, name, make, theta, eps, n_leaf, n_grp)
     ctx.close()
 
 
+def test_fp32_tile_256_forces(torch_cuda):
+    """The FP32 kernel with 256-source tiles on a ring with groups of 300 and
+    of 64 particles (full, partial and second-pass chunks, node and particle
+    tiles) against the oracle on the same lists; and the same lists as the
+    512-source kernel."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    s = inputs.ring(20000, 19)
+    for n_grp in (300, 64):
+        _log(f"[gpu] fp32 tile 256: ring n=20000 seed 19, groups of {n_grp}")
+        st = oracle.BHState(s.x, s.y, s.z, s.m, 0.5, 8, n_grp)
+        ctx = bh.Context(theta=0.5, eps=1e-3, n_group=n_grp, precision=bh.FP32_REL, force_tile=256)
+        dev = bh.to_device(s)
+        ctx.build_tree([dev])
+        ctx.make_lists()
+        _compare_structures(ctx, st, s.n)
+        out = {k: torch.zeros(s.n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+        ctx.forces([out])
+        torch.cuda.synchronize()
+        ax, ay, az, _, _ = st.accel(s.x, s.y, s.z, s.m, 1e-3)
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        rel = np.sqrt((g["ax"] - ax) ** 2 + (g["ay"] - ay) ** 2 + (g["az"] - az) ** 2) / \
+            np.sqrt(ax ** 2 + ay ** 2 + az ** 2)
+        fp32_bars(rel, f"tile 256, groups of {n_grp}")
+        assert ctx.query()["force_tile"] == 256
+        ctx.close()
+
+
 def test_batched_systems_match_single(torch_cuda):
     """Several systems in one context: each system's structures and forces
     equal the oracle run on that system alone."""
@@ -485,6 +513,7 @@ def test_autotune_picks_a_candidate_and_keeps_exact_lists(torch_cuda):
     g = ctx.autotune((32, 64, 128, 256), rebuild_every=4)
     assert g in (32, 64, 128, 256)
     assert ctx.query()["n_group_used"] == g and ctx.query()["lists_valid"] == 1
+    assert ctx.query()["force_tile"] in (256, 512)
     st = oracle.BHState(s.x, s.y, s.z, s.m, 0.5, 8, g)
     pc_off, pc, pp_off, pp = ctx.export("lists")
     np.testing.assert_array_equal(pc_off, st.pc_off)
@@ -493,15 +522,17 @@ def test_autotune_picks_a_candidate_and_keeps_exact_lists(torch_cuda):
     ctx.close()
 
 
-def test_fp32_every_partial_chunk_size(torch_cuda):
+@pytest.mark.parametrize("tile", [512, 256])
+def test_fp32_every_partial_chunk_size(torch_cuda, tile):
     """One system per size 1..300, each a single group (n_group 512): every
     partial-chunk form of the FP32 kernel (8-, 16- and 32-lane sub-slices,
     eighths mode, tail mode, full chunks, and a second pass for groups above
-    256) meets the FP32 bar.  Inside one group no node is accepted, so each
-    system's answer is its direct sum, from the oracle."""
+    256) meets the FP32 bar, with either source tile.  Inside one group no
+    node is accepted, so each system's answer is its direct sum, from the
+    oracle."""
     torch = torch_cuda
     from paper_1907_02289_amd import bh
-    _log("[gpu] fp32, systems of 1..300 particles")
+    _log(f"[gpu] fp32, systems of 1..300 particles, tile {tile}")
     rng = np.random.default_rng(31)
     systems = []
     for c in range(1, 301):
@@ -512,7 +543,7 @@ def test_fp32_every_partial_chunk_size(torch_cuda):
     for x, y, z, m in systems:
         t = {k: torch.as_tensor(v, device="cuda") for k, v in (("x", x), ("y", y), ("z", z), ("m", m))}
         dev.append(t)
-    ctx = bh.Context(theta=0.5, eps=1e-3, n_group=512, precision=bh.FP32_REL)
+    ctx = bh.Context(theta=0.5, eps=1e-3, n_group=512, precision=bh.FP32_REL, force_tile=tile)
     ctx.build_tree(dev)
     ctx.make_lists()
     assert ctx.query()["n_groups"] == len(systems)
