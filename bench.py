@@ -4,22 +4,30 @@
 
 Workload: the 2^24-particle thin ring (r in [1.0, 1.2], z ~ N(0, 5e-4),
 central unit mass, Keplerian velocities with 1e-4 dispersion), eps = 1e-4,
-dt = 1e-3, tree and lists rebuilt every 4 steps with moments refreshed on
-the other steps.  One benchmark step = one rebuild cycle = 4 kick-drift-kick
-steps: keys, sort, tree, moments, groups, walk and lists once, moments three
-more times, four force evaluations and the integration.
+dt = 1e-3.  A benchmark step is one kick-drift-kick step: one force
+evaluation with its share of tree and list builds.  The run starts with a
+force evaluation at t = 0 (bh_step with no steps), then W warm-up steps,
+then the K timed steps.
 
-Before timing, theta is tuned per path so that the 99th percentile of the
-relative self-gravity force error over 4096 sampled particles (against the
-library's FP64 direct sum) is at most 1e-3:
-  tuned: FP32 interactions on group-relative coordinates, groups <= 256,
-         lists reused for 4 steps, persistent longest-first force kernel;
-  plain: FP64 interactions, groups <= 64, lists rebuilt every step.
+Matched error.  For each path the opening parameter is set to the loosest
+value whose force error stays within p99 <= 1e-3 at EVERY force evaluation
+of the run through the last timed one (the 99th percentile, nearest rank, of
+|a - a_direct| / |a_direct| over 4096 sampled particles, self-gravity only,
+against the library's FP64 direct sum at the same positions).  Each trial
+value is a full untimed run from t = 0; the matched run's per-evaluation
+errors are the ones reported.
+  tuned:   FP32 interactions on group-relative coordinates, group size
+           chosen by measured time per step at matched error, lists reused
+           until the drift monitor asks for a rebuild (at most every 16th
+           step), reuse steps replayed from a HIP graph;
+  plain:   FP64 interactions, groups <= 64, lists rebuilt every step;
+  learned: the tuned path with the learned opening rule (network trained
+           on the GPU by the library's kernels on separate rings and a
+           Plummer sphere), its budget tau matched the same way.
 The JSON line reports the tuned path's interactions/s (whole job, inputs
-resident in device memory) and, alongside, the plain path and the oracle.
-The "collisions" object times the tuned path again with the collision branch
-of Eq. (2) on: particle radius from an optical depth of 0.5 over the ring's
-area, r_coll = 2 radii, contact time 32 steps, restitution 0.5.
+resident in device memory, timed window only) and, alongside, the plain and
+learned paths on the same steps, the collision branch of Eq. (2), the
+batched 64-Plummer-sphere workload, and the oracle on the host cores.
 """
 import argparse
 import hashlib
@@ -37,7 +45,18 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_INTERACTION = 19          # 3 sub, 3 fma, rsqrt, 3 mul, 3 fma (fma = 2 flops)
 PAPER_FLOPS_PER_INTERACTION = 31    # the paper's count for a particle-cell interaction
 FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
 TARGET_P99 = 1e-3
+GROUP_SIZES = (256, 512)
+REUSE_MAX = 16                      # longest list age of the tuned path
+# drift monitor of the tuned path: rebuild when, at some tree level, nodes
+# whose particles moved by more than their side relative to the node's centre
+# of mass since the build hold more than 5% of the particles (on the 16M ring
+# this keeps the largest p99 along a 101-evaluation run at that of lists
+# rebuilt every step, with half the builds)
+DRIFT = dict(reuse_drift=1.0, reuse_frac=0.05)
+LEARNED_BAND = (0.03, 0.5)
+THETA_FLOOR = 0.02
 
 
 def log(*a):
@@ -50,92 +69,231 @@ def p99_nearest_rank(e):
     return float(np.sort(e)[int(math.ceil(0.99 * e.size)) - 1])
 
 
-def rel_err_p99(ctx, dev, targets, ref, n):
+class Judge:
+    """Force error of a context's last evaluation on the sample, on the
+    device: the library's FP64 direct sum at the caller's current positions
+    against the sampled accelerations (bh_sample_acc) with the central
+    planet's exact term taken back out."""
+
+    def __init__(self, bh, w, sample):
+        import torch
+        self.torch = torch
+        self.ctx = bh.Context(theta=0.5, eps=w.eps)
+        self.sample = sample
+        self.gm = w.central_mass
+        z = lambda: torch.zeros(sample.numel(), dtype=torch.float64, device="cuda")
+        self.ref = {k: z() for k in ("ax", "ay", "az")}
+        self.got = {k: z() for k in ("ax", "ay", "az")}
+        self.k = int(math.ceil(0.99 * sample.numel()))
+
+    def reference(self, dev):
+        self.ctx.direct_sum(dev, self.sample, self.ref)
+
+    def errors(self, ctx, dev, fresh_reference=True):
+        torch = self.torch
+        if fresh_reference:
+            self.reference(dev)
+        ctx.sample_acc(self.sample, self.got)
+        x, y, z = (dev[f][self.sample] for f in ("x", "y", "z"))
+        r3 = (x * x + y * y + z * z) ** 1.5
+        a = torch.stack([self.got["ax"] + self.gm * x / r3, self.got["ay"] + self.gm * y / r3,
+                         self.got["az"] + self.gm * z / r3])
+        r = torch.stack([self.ref["ax"], self.ref["ay"], self.ref["az"]])
+        e = torch.linalg.vector_norm(a - r, dim=0) / torch.linalg.vector_norm(r, dim=0)
+        s = torch.sort(e).values
+        return float(s[self.k - 1]), float(s[(s.numel() - 1) // 2])
+
+    def close(self):
+        self.ctx.close()
+
+
+def make_ctx(bh, w, p):
+    kw = dict(theta=p["theta"], eps=w.eps, central_mass=w.central_mass, precision=p["precision"],
+              n_group=p["n_group"], cyl_radius=p.get("cyl_radius", 0.0), force_tile=p.get("force_tile", 0))
+    kw.update(p.get("drift", {}))
+    kw.update(p.get("learned", {}))
+    kw.update(p.get("contact", {}))
+    ctx = bh.Context(**kw)
+    if "weights" in p:
+        ctx.mlp_weights(set=p["weights"])
+    return ctx
+
+
+def error_run(bh, w, dev0, judge, p, n_evals, timed_from=None):
+    """The run of configuration p from t = 0 through n_evals force
+    evaluations (untimed): after each evaluation its sampled accelerations
+    are judged against the direct sum.  Also returns the device time of each
+    leapfrog step (HIP events around the step) from evaluation timed_from on,
+    and the number of tree builds."""
     import torch
-    # potentials requested too: the tuning launches use the potential-computing
-    # variant of the force kernel, so per-kernel profiles of the timed variant
-    # hold only timed-configuration launches
-    out = {k: torch.zeros(n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az", "pot")}
-    ctx.forces([out])
-    a = torch.stack([out["ax"][targets], out["ay"][targets], out["az"][targets]])
-    r = torch.stack([ref["ax"], ref["ay"], ref["az"]])
-    e = (torch.linalg.vector_norm(a - r, dim=0) / torch.linalg.vector_norm(r, dim=0)).cpu().numpy()
-    return p99_nearest_rank(e), float(np.median(e))
+    dev = {k: v.clone() for k, v in dev0.items()}
+    ctx = make_ctx(bh, w, p)
+    ctx.step([dev], w.dt, 0, p["rebuild_every"])
+    p99, p50, step_ms = [], [], []
+    e = judge.errors(ctx, dev)
+    p99.append(e[0])
+    p50.append(e[1])
+    for k in range(1, n_evals):
+        ctx.step_continue(w.dt, 1, p["rebuild_every"])
+        if timed_from is not None and k >= timed_from:
+            step_ms.append(ctx.stage_times()["step"])
+        e = judge.errors(ctx, dev)
+        p99.append(e[0])
+        p50.append(e[1])
+    q = ctx.query()
+    ctx.close()
+    del dev
+    torch.cuda.empty_cache()
+    return dict(p99=p99, p50=p50, max=max(p99), step_ms=step_ms, builds=q["tree_builds"],
+                drift_rebuilds=q["drift_rebuilds"], interactions=q["interactions_evaluated"])
 
 
-def tune_theta(ctx, dev, targets, ref, n, lo=0.1, hi=1.0, iters=10):
-    """Largest theta (on a 2^-iters grid of [lo, hi]) with p99 <= TARGET_P99."""
+def first_eval_theta(bh, w, dev0, judge, p, lo=THETA_FLOOR, hi=1.0, iters=10):
+    """Largest theta (on a 2^-iters grid of [lo, hi]) with p99 <= 1e-3 at the
+    first force evaluation, fresh lists.  Raises if even lo misses."""
+    ctx = make_ctx(bh, w, dict(p, theta=hi))
+    ctx.build_tree([dev0])
+    judge.reference(dev0)
+
     def p99(th):
         ctx.set_params(theta=th)
         ctx.make_lists()
-        return rel_err_p99(ctx, dev, targets, ref, n)
-    e_hi = p99(hi)
-    if e_hi[0] <= TARGET_P99:
-        return hi, e_hi
-    best = (lo, p99(lo))
-    for _ in range(iters):
-        mid = 0.5 * (lo + hi)
-        e = p99(mid)
-        if e[0] <= TARGET_P99:
-            lo, best = mid, (mid, e)
+        ctx.forces(None)
+        return judge.errors(ctx, dev0, fresh_reference=False)[0]
+
+    try:
+        if p99(hi) <= TARGET_P99:
+            return hi
+        ok = None
+        for _ in range(iters):
+            mid = 0.5 * (lo + hi)
+            if p99(mid) <= TARGET_P99:
+                lo = ok = mid
+            else:
+                hi = mid
+        if ok is None:
+            # every trial missed: the floor itself decides (small theta means
+            # long lists: a failure to allocate them is a miss as well)
+            try:
+                missed = p99(lo) > TARGET_P99
+            except bh.BHError:
+                missed = True
+            if missed:
+                raise RuntimeError(f"theta {lo} misses p99 <= {TARGET_P99} at the first evaluation")
+        return lo
+    finally:
+        ctx.close()
+
+
+def first_eval_tau(bh, w, dev0, judge, p, lo=-10.0, hi=0.0, iters=12):
+    """Largest tau (log10 on a 2^-iters grid of [lo, hi]) of the learned rule
+    with p99 <= 1e-3 at the first force evaluation."""
+    ctx = make_ctx(bh, w, p)
+    ctx.build_tree([dev0])
+    judge.reference(dev0)
+
+    def p99(lt):
+        ctx.set_params(tau=10.0 ** lt)
+        ctx.make_lists()
+        ctx.forces(None)
+        return judge.errors(ctx, dev0, fresh_reference=False)[0]
+
+    try:
+        ok = None
+        for _ in range(iters):
+            mid = 0.5 * (lo + hi)
+            if p99(mid) <= TARGET_P99:
+                lo = ok = mid
+            else:
+                hi = mid
+        if ok is None and p99(lo) > TARGET_P99:
+            raise RuntimeError(f"learned: tau 1e{lo} misses p99 <= {TARGET_P99} at the first evaluation")
+        return 10.0 ** lo
+    finally:
+        ctx.close()
+
+
+def match_along_run(name, run, x0, alpha, floor, max_runs=6, tol=0.015, guess=None):
+    """Largest x <= x0 (theta, or the learned rule's tau) whose run keeps
+    p99 <= 1e-3 at every evaluation; the error grows with x.  Starts at
+    `guess` (default x0); secant steps on log(max p99) against log(x), a
+    power law of exponent alpha until two points bracket the target; at most
+    max_runs runs.  Returns (x, run record); raises when no trial down to the
+    floor meets the target."""
+    seen = {}
+    ok = bad = None
+    x = min(guess, x0) if guess else x0
+    for it in range(max_runs):
+        r = run(x)
+        seen[x] = r
+        log(f"[bench] {name}: {x:.6g} -> max p99 along the run {r['max']:.4e} ({r['builds']} tree builds)")
+        if r["max"] <= TARGET_P99:
+            ok = x if ok is None else max(ok, x)
         else:
-            hi = mid
-    return best[0], best[1]
+            bad = x if bad is None else min(bad, x)
+        if ok is not None and bad is not None:
+            if (bad - ok) / bad < tol:
+                break
+            m_ok, m_bad = seen[ok]["max"], seen[bad]["max"]
+            slope = math.log(m_bad / m_ok) / math.log(bad / ok) if m_bad > m_ok else alpha
+            xn = ok * (0.99 * TARGET_P99 / m_ok) ** (1.0 / max(slope, 0.25))
+            x = min(max(xn, ok + 0.2 * (bad - ok)), bad - 0.2 * (bad - ok))
+        elif ok is not None:
+            if ok >= x0:
+                break
+            xn = min(x0, ok * (0.99 * TARGET_P99 / seen[ok]["max"]) ** (1.0 / alpha))
+            if xn <= ok * (1.0 + tol):
+                break
+            x = xn
+        else:
+            xn = bad * (0.97 * TARGET_P99 / seen[bad]["max"]) ** (1.0 / alpha)
+            if xn <= floor:
+                if bad <= floor:
+                    raise RuntimeError(f"{name}: p99 {seen[bad]['max']:.3e} > {TARGET_P99} at the floor {floor}")
+                xn = floor
+            x = xn
+    if ok is None:
+        raise RuntimeError(f"{name}: no setting within {max_runs} runs keeps p99 <= {TARGET_P99}")
+    return ok, seen[ok]
 
 
-def error_run(bh, w, dev0, sample, p, n_evals):
-    """Force error of a configuration along its own trajectory (untimed):
-    the run starts like the timed one, and after each of its first n_evals
-    force evaluations the accelerations of that evaluation (the central
-    planet's exact term taken back out: self-gravity only) are compared on
-    the sample with the FP64 direct sum at the same positions.  Returns the
-    p99 (nearest rank) and the median of each evaluation; evaluation k uses
-    lists built k mod rebuild_every evaluations earlier."""
+def timed(bh, w, dev0, p, steps, warmup):
+    """Wall time of `steps` leapfrog steps after `warmup` ones (from the same
+    t = 0 start as the error runs), with HIP-event force-kernel times."""
     import torch
     dev = {k: v.clone() for k, v in dev0.items()}
-    ctx = bh.Context(theta=p["theta"], eps=w.eps, central_mass=w.central_mass, precision=p["precision"],
-                     n_group=p["n_group"], cyl_radius=p.get("cyl_radius", 0.0))
-    judge = bh.Context(theta=0.5, eps=w.eps)
-    tg = sample.cpu().numpy()
-    ref = {k: torch.zeros(sample.numel(), dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
-    gmc = w.central_mass * 1.0
-    out, med = [], []
+    ctx = make_ctx(bh, w, p)
     ctx.step([dev], w.dt, 0, p["rebuild_every"])
-    for k in range(n_evals):
-        if k:
-            ctx.step_continue(w.dt, 1, p["rebuild_every"])
-        judge.direct_sum(dev, sample, ref)
-        torch.cuda.synchronize()
-        acc = ctx.export("acc_sorted")
-        inv = np.empty(acc.shape[0], np.int64)
-        inv[ctx.export("perm").astype(np.int64)] = np.arange(acc.shape[0])
-        a = acc[inv[tg], :3]
-        pos = np.stack([dev[f][sample].cpu().numpy() for f in ("x", "y", "z")], 1)
-        a = a + gmc * pos / (np.sum(pos * pos, 1) ** 1.5)[:, None]
-        r = np.stack([ref[f].cpu().numpy() for f in ("ax", "ay", "az")], 1)
-        e = np.linalg.norm(a - r, axis=1) / np.linalg.norm(r, axis=1)
-        out.append(p99_nearest_rank(e))
-        med.append(float(np.median(e)))
-        del acc
+    if warmup:
+        ctx.step_continue(w.dt, warmup, p["rebuild_every"])
+    torch.cuda.synchronize()
+    ctx.force_timing(reset=True)
+    q0 = ctx.query()
+    t0 = time.perf_counter()
+    ctx.step_continue(w.dt, steps, p["rebuild_every"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    q1 = ctx.query()
+    fms, fl = ctx.force_timing(reset=True)
+    res = dict(wall=wall, interactions=q1["interactions_evaluated"] - q0["interactions_evaluated"],
+               force_evals=q1["force_evaluations"] - q0["force_evaluations"],
+               builds=q1["tree_builds"] - q0["tree_builds"], force_ms=fms, force_launches=fl,
+               host_syncs=q1["host_syncs"] - q0["host_syncs"],
+               n_groups=q1["n_groups"], n_nodes=q1["n_nodes"], stages=ctx.stage_times())
     ctx.close()
-    judge.close()
     del dev
     torch.cuda.empty_cache()
-    return out, med
+    return res
 
 
-GROUP_SIZES = (128, 256, 512)
-LEARNED_BAND = (0.03, 0.5)
-
-
-def learned_path(bh, inputs, w, dev0, sample, ref, n, tuned, args):
-    """The learned opening rule: trained on separate 1M-particle rings and a
-    Plummer sphere (seeds 100-102) with the library's training kernels, then
-    tau bisected to p99 <= 1e-3 on the benchmark ring."""
+def train_learned(bh, inputs, w, n_group, theta):
+    """The learned rule's network, trained by the library's kernels on pairs
+    it collects from separate 1M-particle rings and a Plummer sphere
+    (seeds 100-102, disjoint from the benchmark ring's)."""
     import torch
     lo, hi = LEARNED_BAND
-    kw = dict(criterion=bh.LEARNED, theta_min=lo, theta_max=hi, tau=1e-4)
-    tr = bh.Context(theta=tuned["theta"], eps=w.eps, precision=bh.FP32_REL, n_group=tuned["n_group"], **kw)
+    tr = bh.Context(theta=theta, eps=w.eps, precision=bh.FP32_REL, n_group=n_group, criterion=bh.LEARNED,
+                    theta_min=lo, theta_max=hi, tau=1e-4)
     for sysm in (inputs.ring(1 << 20, 100, central_mass=1.0),
                  inputs.ring(1 << 20, 101, r_out=1.2, z_sigma=5e-4, central_mass=1.0),
                  inputs.plummer(1 << 19, 102)):
@@ -146,32 +304,7 @@ def learned_path(bh, inputs, w, dev0, sample, ref, n, tuned, args):
     weights = tr.mlp_weights()
     tr.close()
     torch.cuda.empty_cache()
-    log(f"[bench] learned: {n_pairs} training pairs, mse {mse:.3f}")
-    ctx = bh.Context(theta=tuned["theta"], eps=w.eps, precision=bh.FP32_REL, n_group=tuned["n_group"], **kw)
-    ctx.mlp_weights(set=weights)
-    ctx.build_tree([dev0])
-
-    def err(lt):
-        ctx.set_params(tau=10.0 ** lt)
-        ctx.make_lists()
-        return rel_err_p99(ctx, dev0, sample, ref, n)
-
-    a, b, best = -9.0, 1.0, None
-    for _ in range(12):
-        mid = 0.5 * (a + b)
-        e = err(mid)
-        if e[0] <= TARGET_P99:
-            a, best = mid, (mid, e)
-        else:
-            b = mid
-    ctx.close()
-    torch.cuda.empty_cache()
-    lt, e = best
-    log(f"[bench] learned: tau=1e{lt:.3f} p99={e[0]:.3e}")
-    p = dict(tuned)
-    p.update(learned=dict(kw, tau=10.0 ** lt), weights=weights, p99=e[0], p50=e[1], training_pairs=n_pairs,
-             training_mse=mse, tree="cartesian", cyl_radius=0.0)     # the learned rule is Cartesian only
-    return p
+    return weights, n_pairs, mse
 
 
 def collision_params(w, tau_opt=0.5, steps_per_contact=32, restitution=0.5):
@@ -191,83 +324,42 @@ def collision_params(w, tau_opt=0.5, steps_per_contact=32, restitution=0.5):
         optical_depth=tau_opt, t_contact=t_c, restitution=restitution)
 
 
-REUSE_INTERVALS = (1, 2, 4, 8, 16)
-
-
-def reuse_study(bh, w, dev0, sample, n, n_group, steps, cyl_radius=0.0, theta_lo=0.05, theta_hi=0.2, iters=7):
-    """Interaction-list reuse (persistent lists): for each rebuild interval R,
-    the loosest theta whose force error stays within p99 <= 1e-3 at every
-    list age 0..R-1 of a cycle (positions moved by the leapfrog, moments
-    refreshed, the judge recomputed at each age), then the time per step of
-    that configuration.  Returns one record per R."""
+def batched_leg(bh, inputs, steps):
+    """The batched workload: 64 Plummer spheres (N log-uniform in [1e3,
+    2e5]) in one context, one launch per stage, FP32, theta 0.6, eps 1e-2,
+    rebuilt every step, group size and force tile autotuned by bh_autotune;
+    `steps` leapfrog steps timed after one warm-up step."""
     import torch
-    judge = bh.Context(theta=0.5, eps=w.eps)
-    gmc = w.central_mass * 1.0
-
-    def cycle_errors(theta, R):
-        dev = {k: v.clone() for k, v in dev0.items()}
-        ctx = bh.Context(theta=theta, eps=w.eps, central_mass=w.central_mass, precision=bh.FP32_REL,
-                         n_group=n_group, cyl_radius=cyl_radius)
-        big = 1 << 30                         # never rebuild inside the cycle
-        ctx.step([dev], w.dt, 0, big)
-        errs = []
-        for age in range(R):
-            if age:
-                ctx.step_continue(w.dt, 1, big)
-            ref = {k: torch.zeros(sample.numel(), dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
-            judge.direct_sum(dev, sample, ref)
-            out = {k: torch.zeros(n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az", "pot")}
-            ctx.forces([out])
-            x, y, z = dev["x"][sample], dev["y"][sample], dev["z"][sample]
-            r3 = (x * x + y * y + z * z) ** 1.5
-            a = torch.stack([out["ax"][sample] + gmc * x / r3, out["ay"][sample] + gmc * y / r3,
-                             out["az"][sample] + gmc * z / r3])
-            r = torch.stack([ref["ax"], ref["ay"], ref["az"]])
-            e = (torch.linalg.vector_norm(a - r, dim=0) / torch.linalg.vector_norm(r, dim=0)).cpu().numpy()
-            errs.append(p99_nearest_rank(e))
-        inter = ctx.query()["interactions"]
-        ctx.close()
-        del dev
-        return errs, inter
-
-    out = []
-    for R in REUSE_INTERVALS:
-        lo, hi, best = theta_lo, theta_hi, None
-        for _ in range(iters):
-            mid = 0.5 * (lo + hi)
-            errs, inter = cycle_errors(mid, R)
-            if max(errs) <= TARGET_P99:
-                lo, best = mid, (mid, errs, inter)
-            else:
-                hi = mid
-        if best is None:
-            errs, inter = cycle_errors(theta_lo, R)
-            best = (theta_lo, errs, inter)
-        th, errs, inter = best
-        # time `steps` cycles of this configuration
-        dev = {k: v.clone() for k, v in dev0.items()}
-        ctx = bh.Context(theta=th, eps=w.eps, central_mass=w.central_mass, precision=bh.FP32_REL, n_group=n_group,
-                         cyl_radius=cyl_radius)
-        ctx.step([dev], w.dt, 0, R)
-        ctx.step_continue(w.dt, R, R)
-        torch.cuda.synchronize()
-        n_leap = max(R, (steps * 4 // R) * R)
-        t0 = time.perf_counter()
-        ctx.step_continue(w.dt, n_leap, R)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        st = ctx.stage_times()
-        ctx.close()
-        del dev
-        torch.cuda.empty_cache()
-        rec = dict(rebuild_every=R, theta=th, p99_by_age=errs, interactions_per_force_eval_at_build=inter,
-                   s_per_step=wall / n_leap, leapfrog_steps_timed=n_leap,
-                   rebuild_ms=st["keys_sort"] + st["tree"] + st["moments"] + st["groups"] + st["walk"],
-                   force_ms=st["forces"])
-        log(f"[bench] reuse R={R}: theta={th:.4f} max p99={max(errs):.3e} s/step={rec['s_per_step']:.4f}")
-        out.append(rec)
-    judge.close()
-    return out
+    w2 = inputs.workload(2)
+    devs = [bh.to_device(s) for s in w2.systems]
+    n_tot = sum(s.n for s in w2.systems)
+    ctx = bh.Context(theta=w2.theta, eps=w2.eps, precision=bh.FP32_REL, n_group=128)
+    ctx.build_tree(devs)
+    chosen = ctx.autotune(candidates=(32, 64, 128, 256, 512), rebuild_every=1)
+    tile = ctx.query()["force_tile"]
+    ctx.close()
+    ctx = bh.Context(theta=w2.theta, eps=w2.eps, precision=bh.FP32_REL, n_group=chosen, force_tile=tile)
+    ctx.step(devs, w2.dt, 1, 1)
+    torch.cuda.synchronize()
+    ctx.force_timing(reset=True)
+    q0 = ctx.query()
+    t0 = time.perf_counter()
+    ctx.step_continue(w2.dt, steps, 1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    q1 = ctx.query()
+    fms, fl = ctx.force_timing(reset=True)
+    st = ctx.stage_times()
+    ctx.close()
+    inter = q1["interactions_evaluated"] - q0["interactions_evaluated"]
+    return dict(workload=f"plummer64_batched_{n_tot}", n_systems=len(w2.systems), n_particles=n_tot,
+                theta=w2.theta, eps=w2.eps, dt=w2.dt, rebuild_every=1, n_group=chosen, force_tile=tile, steps=steps,
+                s_per_step=wall / steps, interactions_per_s=inter / wall,
+                force_kernel_ms=fms / max(1, fl), force_share_of_step=fms / (wall * 1e3),
+                interactions_per_step=inter / steps,
+                host_syncs_per_step=(q1["host_syncs"] - q0["host_syncs"]) / steps,
+                tree_builds_per_step=(q1["tree_builds"] - q0["tree_builds"]) / steps,
+                stages_ms_last=st)
 
 
 def force_source_digest():
@@ -275,7 +367,7 @@ def force_source_digest():
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(workload, n_group, theta, tree):
+def measured_traffic(workload, n_group, theta):
     """HBM bytes per force-kernel launch from the committed rocprofv3 counter
     summaries (one record per configuration), or None when none was taken on
     this workload, configuration and force-kernel source."""
@@ -286,8 +378,7 @@ def measured_traffic(workload, n_group, theta, tree):
         return None
     for rec in (recs if isinstance(recs, list) else [recs]):
         if (rec.get("kernel_source_sha256_16") == force_source_digest() and rec.get("workload") == workload
-                and rec.get("n_group") == n_group and rec.get("theta") == theta
-                and rec.get("tree", "cartesian") == tree):
+                and rec.get("n_group") == n_group and abs(rec.get("theta", -1) - theta) <= 1e-12):
             return rec.get("hbm_bytes_per_launch")
     return None
 
@@ -305,18 +396,14 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "repeats": 3}))
 
 
-def cpu_baseline(system, theta, n_grp, eps, rebuild_every, cyl_radius=0.0, n_sample_groups=16384, seed=0):
-    """The oracle on the host cores: full tree build of the same ring (in the
-    tuned path's tree coordinates), then walk + forces for a random sample of
-    groups; interactions of the sample over the time of the sample's work
-    (build prorated to the sample's share of groups and to one force
-    evaluation of its reuse cycle)."""
+def cpu_baseline(system, theta, n_grp, eps, n_sample_groups=16384, seed=0):
+    """The oracle on the host cores: full tree build of the same ring, then
+    walk + forces for a random sample of groups; interactions of the sample
+    over the time of the sample's work (the build prorated to the sample's
+    share of groups)."""
     import oracle
     t0 = time.perf_counter()
-    if cyl_radius > 0.0:
-        _, _, _, key = oracle.keys_cyl(system.x, system.y, system.z, cyl_radius)
-    else:
-        _, _, _, key = oracle.keys(system.x, system.y, system.z)
+    _, _, _, key = oracle.keys(system.x, system.y, system.z)
     perm = oracle.sort_perm(key)
     skey = key[perm]
     t = oracle.tree(skey, 8)
@@ -328,55 +415,48 @@ def cpu_baseline(system, theta, n_grp, eps, rebuild_every, cyl_radius=0.0, n_sam
     rng = np.random.default_rng(seed)
     sel = np.sort(rng.choice(g.size, min(n_sample_groups, g.size), replace=False))
     t1 = time.perf_counter()
-    pc_off, pc, pp_off, pp = oracle.lists(gbox[sel], t, theta, oracle.CYL_PERIOD if cyl_radius > 0.0 else 0)
+    pc_off, pc, pp_off, pp = oracle.lists(gbox[sel], t, theta)
     oracle.forces(g[sel], t, xs, ys, zs, ms, mom, pc_off, pc, pp_off, pp, eps)
     t_sample = time.perf_counter() - t1
     cnt = t["count"].astype(np.int64)
     pp_len = np.array([cnt[pp[pp_off[k]:pp_off[k + 1]]].sum() for k in range(sel.size)])
     inter = int(np.sum(cnt[g[sel]] * (pp_len + np.diff(pc_off))))
     share = sel.size / g.size
-    t_total = t_sample + t_build * share / rebuild_every
+    t_total = t_sample + t_build * share
     return dict(value=inter / t_total, unit="interactions/s", cores=oracle.n_threads(), kind="oracle",
-                sample=(f"16M ring, theta={theta:.4f}, n_grp={n_grp}, "
-                        f"{'cylindrical' if cyl_radius > 0.0 else 'Cartesian'} tree: oracle tree build of all {system.n} "
-                        f"particles ({t_build:.1f} s, prorated {share:.4f} of groups / {rebuild_every} steps) "
-                        f"+ walk and FP64 forces of {sel.size} random groups ({t_sample:.2f} s, "
-                        f"{inter} interactions)"),
+                sample=(f"16M ring at t = 0, theta={theta:.4f}, n_grp={n_grp}, Cartesian tree: oracle tree build "
+                        f"of all {system.n} particles ({t_build:.1f} s, prorated {share:.4f} of groups) + walk and "
+                        f"FP64 forces of {sel.size} random groups ({t_sample:.2f} s, {inter} interactions)"),
                 seconds=t_build + t_sample)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8, help="timed rebuild cycles (4 leapfrog steps each)")
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--plain-steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=20, help="timed leapfrog steps")
+    ap.add_argument("--warmup", type=int, default=5, help="leapfrog steps before the timed ones")
     ap.add_argument("--n", type=int, default=None, help="particle count override (default 2^24)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="use theta = 0.5 for both paths")
-    ap.add_argument("--n-group", type=int, default=256)
-    ap.add_argument("--tree", choices=("auto", "cartesian", "cylindrical"), default="auto",
-                    help="tree coordinates of the tuned path (auto: whichever is faster at matched error)")
-    ap.add_argument("--theta-tuned", type=float, default=None, help="skip tuning, use this theta (tuned path)")
-    ap.add_argument("--theta-plain", type=float, default=None, help="skip tuning, use this theta (plain path)")
+    ap.add_argument("--legs", default="tuned,plain,learned,collisions,batched",
+                    help="comma-separated legs to run (tuned always runs)")
+    ap.add_argument("--n-group", type=int, default=None, help="tuned path group size (default: autotuned)")
+    ap.add_argument("--tile", type=int, default=None, choices=(256, 512),
+                    help="tuned path force tile (default: autotuned)")
+    ap.add_argument("--theta-tuned", type=float, default=None, help="skip matching, use this theta (tuned path)")
+    ap.add_argument("--theta-plain", type=float, default=None, help="skip matching, use this theta (plain path)")
+    ap.add_argument("--tau-learned", type=float, default=None, help="skip matching, use this tau (learned path)")
+    ap.add_argument("--no-error-runs", action="store_true",
+                    help="with fixed parameters: skip the untimed runs that report the error along the run")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
-    ap.add_argument("--no-collisions", action="store_true", help="skip timing the collision branch")
-    ap.add_argument("--match-along-run", action="store_true",
-                    help="match theta on the largest p99 over the force evaluations of the error run (see "
-                         "--error-evals) instead of on the first one")
-    ap.add_argument("--error-evals", type=int, default=None,
-                    help="force evaluations of the untimed runs that report each path's error along its "
-                         "trajectory (default: through the last timed evaluation of the tuned path; 0: skip)")
     ap.add_argument("--reuse-study", action="store_true",
-                    help="only the list-reuse study: matched-error theta and time per step for each rebuild interval")
-    ap.add_argument("--learned", action="store_true",
-                    help="also train, tune and time the learned-criterion form (off by default: its training-pair "
-                         "collection is kept off the GPU after an unexplained silent test run)")
+                    help="only the list-reuse study: fixed rebuild intervals and the drift monitor, each matched "
+                         "along the run, and their time per step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: sharding the groups "
               f"over several GPUs is a design, not implemented.", file=sys.stderr)
         sys.exit(2)
+    legs = set(args.legs.split(",")) | {"tuned"}
 
     import torch
     from paper_1907_02289_amd import bh, inputs
@@ -388,179 +468,147 @@ def main():
     w = inputs.workload(3, n=args.n)
     sysm = w.systems[0]
     n = sysm.n
-    R = w.rebuild_every
-    if args.error_evals is None:
-        # the first evaluation, the warm-up cycles and the timed cycles
-        args.error_evals = 1 + R * (args.warmup + args.steps)
-    log(f"[bench] ring n={n} rebuild_every={R}")
+    n_evals = 1 + args.warmup + args.steps
+    log(f"[bench] ring n={n}, {args.warmup} warm-up + {args.steps} timed leapfrog steps ({n_evals} force evaluations)")
     dev0 = bh.to_device(sysm)
     sample = torch.as_tensor(inputs.force_sample(n, 3).astype(np.int64), device="cuda")
-
-    # ---- judge: FP64 direct sum on the sample (self-gravity only)
-    judge = bh.Context(theta=0.5, eps=w.eps)
-    ref = {k: torch.zeros(sample.numel(), dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+    judge = Judge(bh, w, sample)
     t = time.perf_counter()
-    judge.direct_sum(dev0, sample, ref)
+    judge.reference(dev0)
     torch.cuda.synchronize()
-    log(f"[bench] direct-sum judge on {sample.numel()} targets: {time.perf_counter() - t:.2f} s")
-    judge.close()
+    log(f"[bench] direct-sum judge on {sample.numel()} targets: {time.perf_counter() - t:.3f} s")
 
     if args.reuse_study:
-        r_cyl = np.hypot(sysm.x, sysm.y)
-        cyl = 0.5 * float(r_cyl.min() + r_cyl.max()) if args.tree == "cylindrical" else 0.0
-        recs = reuse_study(bh, w, dev0, sample, n, args.n_group, args.steps, cyl_radius=cyl)
-        best = min(recs, key=lambda r: r["s_per_step"])
-        print(json.dumps({"metric": "list-reuse study: s/step at matched p99 rel force err 1e-3 per rebuild interval",
-                          "config": {"workload": f"ring{n}", "n_group": args.n_group, "eps": w.eps, "dt": w.dt,
-                                     "tree_coordinates": "cylindrical" if cyl else "cartesian", "cyl_radius": cyl},
-                          "fastest_rebuild_every": best["rebuild_every"], "records": recs}), flush=True)
+        reuse_study(bh, w, dev0, judge, n, args)
         return
 
-    # ---- matched error: theta per path (and per group size for the tuned path)
-    paths = {
-        "tuned": dict(precision=bh.FP32_REL, n_group=args.n_group, rebuild_every=R),
-        "plain": dict(precision=bh.FP64, n_group=64, rebuild_every=1),
-    }
-    fixed = {"tuned": args.theta_tuned, "plain": args.theta_plain}
-    group_sizes = [args.n_group] if (args.no_tune or args.theta_tuned is not None) else list(GROUP_SIZES)
-    # tree coordinates of the tuned path: Cartesian, or cylindrical around the
-    # ring's mid radius (Sec. 4.3)
-    r_cyl = np.hypot(sysm.x, sysm.y)
-    cyl_ref = 0.5 * float(r_cyl.min() + r_cyl.max())
-    coords = {"cartesian": 0.0, "cylindrical": cyl_ref}
-    tree_choices = [args.tree] if args.tree != "auto" else list(coords)
+    paths = {}
     autotune = []
-    for name, p in paths.items():
-        best = None
-        for ng, tc in ([(g, t) for t in tree_choices for g in group_sizes] if name == "tuned"
-                       else [(p["n_group"], "cartesian")]):
-            ctx = bh.Context(theta=0.5, eps=w.eps, precision=p["precision"], n_group=ng, cyl_radius=coords[tc])
-            ctx.build_tree([dev0])
-            if args.no_tune or fixed[name] is not None:
-                th = fixed[name] if fixed[name] is not None else 0.5
-                ctx.set_params(theta=th)
-                ctx.make_lists()
-                e = rel_err_p99(ctx, dev0, sample, ref, n)
+    fixed_run = args.no_error_runs
+
+    # ---- tuned path: theta matched along the run, then the group size and
+    # the force tile by measured time per step at that theta (the error at a
+    # given theta hardly depends on the group size: a changed choice is
+    # checked by a run of its own)
+    base = dict(precision=bh.FP32_REL, n_group=args.n_group or GROUP_SIZES[0], force_tile=512,
+                rebuild_every=REUSE_MAX, drift=dict(DRIFT))
+    r = None
+    if args.theta_tuned is not None:
+        base["theta"] = args.theta_tuned
+    else:
+        th0 = first_eval_theta(bh, w, dev0, judge, base)
+        base["theta_first_eval"] = th0
+        base["theta"], r = match_along_run(
+            f"tuned n_group={base['n_group']} theta",
+            lambda th: error_run(bh, w, dev0, judge, dict(base, theta=th), n_evals, 1 + args.warmup),
+            th0, 2.0, THETA_FLOOR)
+    best = None
+    sizes = [args.n_group] if args.n_group else list(GROUP_SIZES)
+    tiles = [args.tile] if args.tile else [512, 256]
+    cands = [(ng, tile) for ng in sizes for tile in tiles]
+    for ng, tile in cands if len(cands) > 1 else []:
+        p = dict(base, n_group=ng, force_tile=tile)
+        t = timed(bh, w, dev0, p, args.steps, args.warmup)
+        cost = t["wall"] / args.steps * 1e3
+        autotune.append(dict(n_group=ng, force_tile=tile, theta=p["theta"], ms_per_step=cost))
+        log(f"[bench] tuned n_group={ng} tile={tile}: {cost:.2f} ms/step")
+        if best is None or cost < best[0]:
+            best = (cost, p)
+    p = best[1] if best else dict(base, n_group=cands[0][0], force_tile=cands[0][1])
+    if r is None or (p["n_group"], p["force_tile"]) != (base["n_group"], base["force_tile"]):
+        if not fixed_run:
+            r2 = error_run(bh, w, dev0, judge, p, n_evals, 1 + args.warmup)
+            if r is not None and r2["max"] > TARGET_P99:
+                log(f"[bench] n_group={p['n_group']} tile={p['force_tile']}: max p99 {r2['max']:.3e} misses; "
+                    f"keeping n_group={base['n_group']} tile={base['force_tile']}")
+                p = base
             else:
-                th, e = tune_theta(ctx, dev0, sample, ref, n)
-            ctx.set_params(theta=th)
-            ctx.make_lists()
-            inter = ctx.query()["interactions"]
-            ctx.close()
-            cost = None
-            if name == "tuned" and len(group_sizes) * len(tree_choices) > 1:
-                # cost at this theta where the timed region starts: the wall time
-                # per leapfrog step of one rebuild cycle after the same warm-up
-                cdev = {k: v.clone() for k, v in dev0.items()}
-                cc = bh.Context(theta=th, eps=w.eps, central_mass=w.central_mass, precision=p["precision"],
-                                n_group=ng, cyl_radius=coords[tc])
-                cc.step([cdev], w.dt, 0, R)
-                for _ in range(args.warmup):
-                    cc.step_continue(w.dt, R, R)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                cc.step_continue(w.dt, R, R)
-                torch.cuda.synchronize()
-                cost = (time.perf_counter() - t0) * 1e3 / R
-                cc.close()
-                del cdev
-            log(f"[bench] {name} n_group={ng} {tc}: theta={th:.4f} p99={e[0]:.3e}"
-                + (f" cost {cost:.2f} ms per step after warm-up" if cost is not None else ""))
-            if name == "tuned":
-                autotune.append({"n_group": ng, "tree": tc, "theta": th, "p99": e[0],
-                                 "interactions_per_force_eval": inter,
-                                 "ms_per_step_after_warmup": cost})
-            if best is None or (cost is not None and cost < best[0]):
-                best = (cost, ng, th, e, tc)
-            torch.cuda.empty_cache()
-        p["n_group"], p["theta"], (p["p99"], p["p50"]), p["tree"] = best[1], best[2], best[3], best[4]
-        p["cyl_radius"] = coords[best[4]]
+                r = r2
+    paths["tuned"] = dict(p, run=r)
 
-    # ---- optionally: theta matched on the whole run, bisected below the
-    # first-evaluation value (the error grows as the ring evolves)
-    if args.match_along_run and args.error_evals > 0:
-        for name, p in paths.items():
-            hi = p["theta"]
-            lo, best = 0.5 * hi, None
-            e = error_run(bh, w, dev0, sample, p, args.error_evals)
-            if max(e[0]) <= TARGET_P99:
-                best = (hi, e)
-            else:
-                for _ in range(6):
-                    mid = 0.5 * (lo + hi)
-                    e = error_run(bh, w, dev0, sample, dict(p, theta=mid), args.error_evals)
-                    log(f"[bench] {name}: theta {mid:.4f}: max p99 along the run {max(e[0]):.3e}")
-                    if max(e[0]) <= TARGET_P99:
-                        lo, best = mid, (mid, e)
-                    else:
-                        hi = mid
-                if best is None:
-                    best = (lo, error_run(bh, w, dev0, sample, dict(p, theta=lo), args.error_evals))
-            log(f"[bench] {name}: theta {p['theta']:.4f} matched at the first evaluation, {best[0]:.4f} over "
-                f"{args.error_evals} (max p99 {max(best[1][0]):.3e})")
-            p["theta_first_eval"] = p["theta"]
-            p["theta"] = best[0]
-            p["p99"], p["p50"] = best[1][0][0], best[1][1][0]
+    # ---- plain path: FP64, groups <= 64, rebuilt every step
+    if "plain" in legs:
+        p = dict(precision=bh.FP64, n_group=64, rebuild_every=1)
+        if args.theta_plain is not None:
+            p["theta"] = args.theta_plain
+            r = None if fixed_run else error_run(bh, w, dev0, judge, p, n_evals)
+        else:
+            th0 = first_eval_theta(bh, w, dev0, judge, p)
+            p["theta_first_eval"] = th0
+            # first guess: the tuned path's ratio of along-the-run to first-evaluation theta
+            tp = paths["tuned"]
+            guess = th0 * tp["theta"] / tp["theta_first_eval"] if "theta_first_eval" in tp else None
+            p["theta"], r = match_along_run(
+                "plain theta", lambda th: error_run(bh, w, dev0, judge, dict(p, theta=th), n_evals), th0, 2.0,
+                THETA_FLOOR, guess=guess)
+        paths["plain"] = dict(p, run=r)
 
-    # ---- timed runs
-    def timed(p, steps, warmup, leap_per_step):
-        dev = {k: v.clone() for k, v in dev0.items()}
-        ctx = bh.Context(theta=p["theta"], eps=w.eps, central_mass=w.central_mass, precision=p["precision"],
-                         n_group=p["n_group"], cyl_radius=p.get("cyl_radius", 0.0), **p.get("learned", {}),
-                         **p.get("contact", {}))
-        if "weights" in p:
-            ctx.mlp_weights(set=p["weights"])
-        ctx.step([dev], w.dt, 0, p["rebuild_every"])
-        for _ in range(warmup):
-            ctx.step_continue(w.dt, leap_per_step, p["rebuild_every"])
-        torch.cuda.synchronize()
-        ctx.force_timing(reset=True)
-        q0 = ctx.query()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            ctx.step_continue(w.dt, leap_per_step, p["rebuild_every"])
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        q1 = ctx.query()
-        fms, fl = ctx.force_timing(reset=True)
-        res = dict(wall=wall, interactions=q1["interactions_evaluated"] - q0["interactions_evaluated"],
-                   force_evals=q1["force_evaluations"] - q0["force_evaluations"],
-                   builds=q1["tree_builds"] - q0["tree_builds"], force_ms=fms, force_launches=fl,
-                   n_groups=q1["n_groups"], n_nodes=q1["n_nodes"], stages=ctx.stage_times())
-        ctx.close()
-        del dev
-        torch.cuda.empty_cache()
-        return res
+    # ---- learned opening rule on the tuned configuration
+    if "learned" in legs:
+        tp = paths["tuned"]
+        lo, hi = LEARNED_BAND
+        t = time.perf_counter()
+        weights, n_pairs, mse = train_learned(bh, inputs, w, tp["n_group"], tp["theta"])
+        t_train = time.perf_counter() - t
+        log(f"[bench] learned: {n_pairs} training pairs, mse {mse:.3f}, {t_train:.1f} s")
+        p = dict(tp, learned=dict(criterion=bh.LEARNED, theta_min=lo, theta_max=hi, tau=1e-4), weights=weights)
+        p.pop("run", None)
+        if args.tau_learned is not None:
+            p["learned"]["tau"] = args.tau_learned
+            r = None if fixed_run else error_run(bh, w, dev0, judge, p, n_evals, 1 + args.warmup)
+        else:
+            def run_tau(tau):
+                return error_run(bh, w, dev0, judge, dict(p, learned=dict(p["learned"], tau=tau)), n_evals,
+                                 1 + args.warmup)
+            tau0 = first_eval_tau(bh, w, dev0, judge, p)
+            # first guess: the error grows along the run as it did for the
+            # tuned path's theta; p99 goes about as tau^(1/2)
+            grow = (tp["theta_first_eval"] / tp["theta"]) ** 2 if "theta_first_eval" in tp else 1.0
+            tau, r = match_along_run("learned tau", run_tau, tau0, 0.5, 1e-14, guess=tau0 / grow ** 2)
+            p["learned"]["tau"] = tau
+            p["tau_first_eval"] = tau0
+        paths["learned"] = dict(p, run=r, training_pairs=n_pairs, training_mse=mse, training_s=t_train)
 
-    tu = timed(paths["tuned"], args.steps, args.warmup, R)
-    log(f"[bench] tuned: {tu}")
-    lr = None
-    if args.learned:
-        lp = learned_path(bh, inputs, w, dev0, sample, ref, n, paths["tuned"], args)
-        lr = timed(lp, max(1, args.steps // 2), 1, R)
-        log(f"[bench] learned: {lr}")
-    pl = timed(paths["plain"], args.plain_steps, 1, 1)
-    log(f"[bench] plain: {pl}")
+    # ---- timed runs (same start, warm-up and steps for every path)
+    res = {}
+    for name in ("tuned", "plain", "learned"):
+        if name in paths:
+            res[name] = timed(bh, w, dev0, paths[name], args.steps, args.warmup)
+            log(f"[bench] {name}: {res[name]}")
     co = None
-    if not args.no_collisions:
+    if "collisions" in legs:
         cparams, cinfo = collision_params(w)
-        co_steps = max(2, args.steps // 2)
-        co = timed(dict(paths["tuned"], contact=cparams), co_steps, 1, R)
+        co = timed(bh, w, dev0, dict(paths["tuned"], contact=cparams), args.steps, args.warmup)
         log(f"[bench] collisions {cparams}: {co}")
+    bat = None
+    if "batched" in legs:
+        bat = batched_leg(bh, inputs, 20)
+        log(f"[bench] batched: {bat}")
+    judge.close()
 
-    errs = {}
-    if args.error_evals > 0:
-        for name in ("tuned", "plain"):
-            errs[name] = error_run(bh, w, dev0, sample, paths[name], args.error_evals)[0]
-            log(f"[bench] {name} path p99 over {len(errs[name])} force evaluations: max {max(errs[name]):.3e}")
-
-    leap_t = tu["wall"] / (args.steps * R)
-    leap_p = pl["wall"] / args.plain_steps
+    tu, tp = res["tuned"], paths["tuned"]
     value = tu["interactions"] / tu["wall"]
     per_launch = tu["interactions"] / max(1, tu["force_evals"])
     avg_ms = tu["force_ms"] / max(1, tu["force_launches"])
     achieved = per_launch * FLOPS_PER_INTERACTION / (avg_ms * 1e-3) / 1e12
-    workload = f"ring{n}_reuse{R}"
+    workload = f"ring{n}_kdk{args.warmup}+{args.steps}"
+
+    def path_record(name):
+        p, r, t = paths[name], paths[name]["run"], res[name]
+        rec = dict(theta=p["theta"], n_group=p["n_group"], force_tile=p.get("force_tile", 512),
+                   s_per_step=t["wall"] / args.steps,
+                   interactions_per_s=t["interactions"] / t["wall"],
+                   interactions_per_force_eval=t["interactions"] / max(1, t["force_evals"]),
+                   tree_builds_timed=t["builds"], host_syncs_timed=t["host_syncs"],
+                   force_kernel_ms=t["force_ms"] / max(1, t["force_launches"]),
+                   dtype="f64" if p["precision"] == bh.FP64 else "f32",
+                   rebuild="every step" if p["rebuild_every"] == 1 else
+                   f"drift monitor {p.get('drift')}, at most every {p['rebuild_every']} steps")
+        if "theta_first_eval" in p:
+            rec["theta_first_eval"] = p["theta_first_eval"]
+        if r is not None:
+            rec["p99_along_run"] = dict(per_force_eval=r["p99"], max=r["max"], p50_max=max(r["p50"]))
+        return rec
 
     out = {
         "metric": "interactions/s & s/step, 16M ring, p99 rel force err 1e-3: tuned vs plain GPU BH",
@@ -576,64 +624,104 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": workload,
-            "n_particles": n, "theta_tuned": paths["tuned"]["theta"], "theta_plain": paths["plain"]["theta"],
-            "eps": w.eps, "dt": w.dt, "rebuild_every": R, "n_group": paths["tuned"]["n_group"],
-            "tree_coordinates": paths["tuned"]["tree"], "cyl_radius": paths["tuned"]["cyl_radius"],
-            "step": f"one rebuild cycle = {R} KDK steps", "positions_and_integration": "f64",
-            "theta_matched_on": (f"largest p99 over the first {args.error_evals} force evaluations"
-                                 if "theta_first_eval" in paths["tuned"] else "first force evaluation"),
+            "workload": workload, "n_particles": n, "eps": w.eps, "dt": w.dt,
+            "step": "one kick-drift-kick step (one force evaluation, tree and list builds as they fall)",
+            "theta_tuned": tp["theta"], "n_group": tp["n_group"], "force_tile": tp["force_tile"],
+            "rebuild": f"drift monitor {tp['drift']}, "
+            f"at most every {tp['rebuild_every']} steps", "positions_and_integration": "f64",
+            "matched_error": (f"p99 <= {TARGET_P99} at every one of the {n_evals} force evaluations through the "
+                              f"last timed one, for each path; theta bracket floor {THETA_FLOOR}"),
         },
-        "s_per_leapfrog_step": leap_t,
+        "s_per_step": tu["wall"] / args.steps,
         "interactions_per_force_eval": per_launch,
-        "p99_rel_err": paths["tuned"]["p99"], "p50_rel_err": paths["tuned"]["p50"],
-        "plain": {"s_per_step": leap_p, "interactions_per_s": pl["interactions"] / pl["wall"],
-                  "p99_rel_err": paths["plain"]["p99"], "dtype": "f64", "n_group": 64, "rebuild_every": 1},
-        "speedup_vs_plain_s_per_step": leap_p / leap_t,
+        "tree_builds_timed": tu["builds"],
+        "tuned": path_record("tuned"),
         "group_size_autotune": autotune,
         "force_kernel_ms": avg_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS,
-                     "traffic": measured_traffic(workload, paths["tuned"]["n_group"], paths["tuned"]["theta"],
-                                                 paths["tuned"]["tree"]),
+                     "traffic": measured_traffic(workload, tp["n_group"], tp["theta"]),
                      "flops_per_interaction": FLOPS_PER_INTERACTION,
                      "frac_at_paper_31_flops": achieved * PAPER_FLOPS_PER_INTERACTION / FLOPS_PER_INTERACTION
                      / FP32_PEAK_TFLOPS},
         "stages_ms_last": tu["stages"],
+        "reproduce_without_matching": (f"--steps {args.steps} --warmup {args.warmup} --n-group {tp['n_group']} "
+                                       f"--tile {tp['force_tile']} --theta-tuned {tp['theta']!r}"
+                                       + (f" --theta-plain {paths['plain']['theta']!r}" if "plain" in paths else "")
+                                       + (f" --tau-learned {paths['learned']['learned']['tau']!r}"
+                                          if "learned" in paths else "")),
     }
-    for name in ("tuned", "plain"):
-        if "theta_first_eval" in paths[name]:
-            out["config"][f"theta_{name}_matched_at_first_eval"] = paths[name]["theta_first_eval"]
-    if errs:
-        # the error along each path's run (theta as matched above), per
-        # evaluation and as the maximum over each of the tuned path's rebuild
-        # cycles
-        out["p99_along_run"] = {
-            name: {"per_force_eval": e, "max_per_4_evals": [max(e[i:i + R]) for i in range(0, len(e), R)],
-                   "max": max(e)} for name, e in errs.items()}
-        out["p99_along_run"]["target"] = TARGET_P99
+    if "plain" in paths:
+        pr = path_record("plain")
+        pl = res["plain"]
+        pms = pl["force_ms"] / max(1, pl["force_launches"])
+        pach = pr["interactions_per_force_eval"] * FLOPS_PER_INTERACTION / (pms * 1e-3) / 1e12
+        pr["force_kernel_fp64_tflops_19"] = pach
+        pr["force_kernel_frac_of_fp64_peak"] = pach / FP64_PEAK_TFLOPS
+        out["plain"] = pr
+        out["speedup_vs_plain_s_per_step"] = pr["s_per_step"] / out["s_per_step"]
+    if "learned" in paths:
+        lr = path_record("learned")
+        lp = paths["learned"]
+        lr.update(tau=lp["learned"]["tau"], tau_first_eval=lp.get("tau_first_eval"), band=list(LEARNED_BAND),
+                  training_pairs=lp["training_pairs"],
+                  training_mse=lp["training_mse"], training_s=lp["training_s"],
+                  interactions_vs_geometric=lr["interactions_per_force_eval"] / per_launch,
+                  s_per_step_vs_geometric=lr["s_per_step"] / out["s_per_step"])
+        if "plain" in out:
+            lr["speedup_vs_plain_s_per_step"] = out["plain"]["s_per_step"] / lr["s_per_step"]
+        out["learned"] = lr
     if co is not None:
         c_launch = co["interactions"] / max(1, co["force_evals"])
         c_ms = co["force_ms"] / max(1, co["force_launches"])
         c_ach = c_launch * FLOPS_PER_INTERACTION / (c_ms * 1e-3) / 1e12
-        out["collisions"] = dict(cparams, **cinfo, s_per_step=co["wall"] / (co_steps * R),
+        out["collisions"] = dict(cparams, **cinfo, s_per_step=co["wall"] / args.steps,
                                  interactions_per_s=co["interactions"] / co["wall"],
                                  interactions_per_force_eval=c_launch, force_kernel_ms=c_ms,
                                  force_kernel_ms_ratio_vs_gravity_only=c_ms / avg_ms,
                                  achieved_tflops_19=c_ach, frac=c_ach / FP32_PEAK_TFLOPS)
-    if lr is not None:
-        lps = lr["wall"] / (max(1, args.steps // 2) * R)
-        out["learned"] = {"s_per_step": lps, "interactions_per_s": lr["interactions"] / lr["wall"],
-                          "interactions_per_force_eval": lr["interactions"] / max(1, lr["force_evals"]),
-                          "tau": lp["learned"]["tau"], "p99_rel_err": lp["p99"], "p50_rel_err": lp["p50"],
-                          "training_pairs": lp["training_pairs"], "training_mse": lp["training_mse"],
-                          "speedup_vs_plain_s_per_step": leap_p / lps,
-                          "interactions_vs_geometric": (lr["interactions"] / max(1, lr["force_evals"])) / per_launch}
+    if bat is not None:
+        out["batched"] = bat
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(sysm, paths["tuned"]["theta"], paths["tuned"]["n_group"], w.eps, R,
-                                           paths["tuned"]["cyl_radius"])
+        out["cpu_baseline"] = cpu_baseline(sysm, tp["theta"], tp["n_group"], w.eps)
     print(json.dumps(out), flush=True)
+
+
+REUSE_INTERVALS = (1, 2, 4, 8)
+
+
+def reuse_study(bh, w, dev0, judge, n, args):
+    """Interaction-list reuse (persistent lists): for each fixed rebuild
+    interval R and for the drift monitor, theta matched so that p99 <= 1e-3
+    at every evaluation of a run of 1 + warmup + steps evaluations, and the
+    device time per step over the last `steps` of them."""
+    n_evals = 1 + args.warmup + args.steps
+    ng = args.n_group or 256
+    recs = []
+    configs = [(f"R={R}", dict(rebuild_every=R)) for R in REUSE_INTERVALS]
+    configs.append(("drift", dict(rebuild_every=REUSE_MAX, drift=dict(DRIFT))))
+    th0 = guess = None
+    for name, extra in configs:
+        p = dict(precision=bh.FP32_REL, n_group=ng, **extra)
+        if th0 is None:
+            th0 = first_eval_theta(bh, w, dev0, judge, p)
+        th, r = match_along_run(f"reuse {name} theta",
+                                lambda th: error_run(bh, w, dev0, judge, dict(p, theta=th), n_evals,
+                                                     1 + args.warmup), th0, 2.0, THETA_FLOOR, max_runs=7,
+                                guess=guess)
+        guess = th
+        rec = dict(config=name, theta=th, max_p99=r["max"], p99_per_force_eval=r["p99"],
+                   device_ms_per_step=float(np.mean(r["step_ms"])), tree_builds=r["builds"],
+                   interactions_per_force_eval=r["interactions"] / n_evals)
+        log(f"[bench] reuse {name}: theta={th:.5f} max p99={r['max']:.3e} "
+            f"{rec['device_ms_per_step']:.2f} ms/step, {r['builds']} builds")
+        recs.append(rec)
+    fastest = min(recs, key=lambda r: r["device_ms_per_step"])
+    print(json.dumps({"metric": "list-reuse study: device ms/step at p99 <= 1e-3 along the whole run",
+                      "config": {"workload": f"ring{n}", "n_group": ng, "eps": w.eps, "dt": w.dt,
+                                 "force_evaluations": n_evals, "timed_from": 1 + args.warmup},
+                      "fastest": fastest["config"], "records": recs}), flush=True)
 
 
 if __name__ == "__main__":

@@ -1,7 +1,9 @@
-"""The benchmark's error along a run maps the library's sorted accelerations
-back to the sampled particles and takes the central planet's term back out.
-At t = 0 that must give the p99 the theta tuning measures directly on a
-context without the planet (same lists, self-gravity only)."""
+"""The benchmark's error along a run reads the sampled accelerations on the
+device (bh_sample_acc) and takes the central planet's term back out.  At
+t = 0 that must give the p99 and median of a direct measurement on a
+context without the planet (same lists, self-gravity only, accelerations
+written in caller order by bh_forces and compared on the host)."""
+import math
 import sys
 import types
 
@@ -19,30 +21,70 @@ def test_error_run_first_evaluation_matches_direct_measurement():
         pytest.skip("no GPU")
     import bench
     from paper_1907_02289_amd import bh
-    print("[gpu] bench error run vs direct measurement", flush=True)
+    print("[gpu] bench error run vs direct measurement: ring n=20000 seed 5, 1024 samples", flush=True)
     sys.stdout.flush()
     s = inputs.ring(20000, 5, central_mass=1.0)
     w = types.SimpleNamespace(eps=1e-4, dt=1e-3, central_mass=1.0)
     dev0 = bh.to_device(s)
-    sample = torch.as_tensor(inputs.force_sample(s.n, 5, 1024).astype(np.int64), device="cuda")
+    tg = inputs.force_sample(s.n, 5, 1024).astype(np.int64)
+    sample = torch.as_tensor(tg, device="cuda")
+    judge = bench.Judge(bh, w, sample)
+    ref = {k: torch.zeros(sample.numel(), dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+    judge.ctx.direct_sum(dev0, sample, ref)
+    r = np.stack([ref[k].cpu().numpy() for k in ("ax", "ay", "az")], 1)
     for prec in (bh.FP32_REL, bh.FP64):
         p = dict(theta=0.4, precision=prec, n_group=128, rebuild_every=4)
-        p99, med = bench.error_run(bh, w, dev0, sample, p, 3)
-        judge = bh.Context(theta=0.5, eps=w.eps)
-        ref = {k: torch.zeros(sample.numel(), dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
-        judge.direct_sum(dev0, sample, ref)
+        run = bench.error_run(bh, w, dev0, judge, p, 3)
         ctx = bh.Context(theta=0.4, eps=w.eps, precision=prec, n_group=128)
         ctx.build_tree([dev0])
         ctx.make_lists()
-        want, want_med = bench.rel_err_p99(ctx, dev0, sample, ref, s.n)
+        out = {k: torch.zeros(s.n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+        ctx.forces([out])
+        torch.cuda.synchronize()
+        a = np.stack([out[k].cpu().numpy()[tg] for k in ("ax", "ay", "az")], 1)
         ctx.close()
-        judge.close()
+        e = np.sort(np.linalg.norm(a - r, axis=1) / np.linalg.norm(r, axis=1))
+        want = float(e[int(math.ceil(0.99 * e.size)) - 1])
+        want_med = float(e[(e.size - 1) // 2])
         # FP64: the same sums up to the planet's term added and taken back;
-        # FP32: the tuning runs the potential-computing kernel instance, whose
-        # FP32 sums may round differently (a relative change of ~1e-7 in a
-        # moves an error of ~1e-3 by ~1e-4 of itself).  A wrong mapping would
-        # be off by orders of magnitude.
+        # FP32: the run's kernel instance (no potential, fused kick) and the
+        # direct call's may round their FP32 sums differently (a relative
+        # change of ~1e-7 in a moves an error of ~1e-3 by ~1e-4 of itself).
+        # A wrong mapping would be off by orders of magnitude.
         tol = 1e-6 if prec == bh.FP64 else 1e-3
-        assert len(p99) == 3 and all(np.isfinite(p99))
-        assert abs(p99[0] - want) <= tol * want, (prec, p99[0], want)
-        assert abs(med[0] - want_med) <= tol * want_med, (prec, med[0], want_med)
+        assert len(run["p99"]) == 3 and all(np.isfinite(run["p99"]))
+        assert abs(run["p99"][0] - want) <= tol * want, (prec, run["p99"][0], want)
+        assert abs(run["p50"][0] - want_med) <= tol * want_med, (prec, run["p50"][0], want_med)
+    judge.close()
+
+
+def test_sample_acc_reads_the_last_evaluation():
+    """bh_sample_acc returns, bit for bit, the accelerations bh_forces writes
+    in caller order, for any subset of indices; an index outside the system
+    gives NaN."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1907_02289_amd import bh
+    print("[gpu] sample_acc: two systems, n=3000 and 5000", flush=True)
+    systems = [inputs.ring(3000, 6, central_mass=1.0), inputs.plummer(5000, 7)]
+    devs = [bh.to_device(s) for s in systems]
+    ctx = bh.Context(theta=0.5, eps=1e-3, central_mass=1.0, precision=bh.FP32_REL, n_group=128)
+    ctx.build_tree(devs)
+    ctx.make_lists()
+    outs = [{k: torch.zeros(s.n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")} for s in systems]
+    ctx.forces(outs)
+    for k, s in enumerate(systems):
+        tg = np.random.default_rng(k).choice(s.n, 700, replace=False).astype(np.int64)
+        tg[5] = s.n                               # out of range: NaN
+        tg[9] = -1
+        tt = torch.as_tensor(tg, device="cuda")
+        got = {q: torch.zeros(tg.size, dtype=torch.float64, device="cuda") for q in ("ax", "ay", "az")}
+        ctx.sample_acc(tt, got, system=k)
+        torch.cuda.synchronize()
+        ok = (tg >= 0) & (tg < s.n)
+        for q in ("ax", "ay", "az"):
+            g = got[q].cpu().numpy()
+            np.testing.assert_array_equal(g[ok], outs[k][q].cpu().numpy()[tg[ok]])
+            assert np.all(np.isnan(g[~ok]))
+    ctx.close()
