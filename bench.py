@@ -438,16 +438,20 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="particle count override (default 2^24)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--legs", default="tuned,plain,learned,collisions,batched",
-                    help="comma-separated legs to run (tuned always runs)")
+                    help="comma-separated legs to run (tuned always runs, unless the batched leg runs alone)")
     ap.add_argument("--n-group", type=int, default=None, help="tuned path group size (default: autotuned)")
     ap.add_argument("--tile", type=int, default=None, choices=(256, 512),
                     help="tuned path force tile (default: autotuned)")
     ap.add_argument("--theta-tuned", type=float, default=None, help="skip matching, use this theta (tuned path)")
     ap.add_argument("--theta-plain", type=float, default=None, help="skip matching, use this theta (plain path)")
     ap.add_argument("--tau-learned", type=float, default=None, help="skip matching, use this tau (learned path)")
+    ap.add_argument("--learned-budget", choices=("mean", "min"), default="mean",
+                    help="the learned rule's budget scale A_g: mean or smallest |a| of a group's particles")
     ap.add_argument("--no-error-runs", action="store_true",
                     help="with fixed parameters: skip the untimed runs that report the error along the run")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
+    ap.add_argument("--reuse-configs", default=None,
+                    help="reuse study: comma-separated subset of R=1,R=2,R=4,R=8,drift, or drift:<kappa>:<frac>")
     ap.add_argument("--reuse-study", action="store_true",
                     help="only the list-reuse study: fixed rebuild intervals and the drift monitor, each matched "
                          "along the run, and their time per step")
@@ -456,7 +460,9 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: sharding the groups "
               f"over several GPUs is a design, not implemented.", file=sys.stderr)
         sys.exit(2)
-    legs = set(args.legs.split(",")) | {"tuned"}
+    legs = set(args.legs.split(","))
+    if legs != {"batched"}:
+        legs |= {"tuned"}
 
     import torch
     from paper_1907_02289_amd import bh, inputs
@@ -480,6 +486,10 @@ def main():
 
     if args.reuse_study:
         reuse_study(bh, w, dev0, judge, n, args)
+        return
+    if legs == {"batched"}:
+        # the batched workload alone (for a profile of that leg)
+        print(json.dumps({"batched": batched_leg(bh, inputs, args.steps)}), flush=True)
         return
 
     paths = {}
@@ -551,7 +561,8 @@ def main():
         weights, n_pairs, mse = train_learned(bh, inputs, w, tp["n_group"], tp["theta"])
         t_train = time.perf_counter() - t
         log(f"[bench] learned: {n_pairs} training pairs, mse {mse:.3f}, {t_train:.1f} s")
-        p = dict(tp, learned=dict(criterion=bh.LEARNED, theta_min=lo, theta_max=hi, tau=1e-4), weights=weights)
+        p = dict(tp, learned=dict(criterion=bh.LEARNED, theta_min=lo, theta_max=hi, tau=1e-4,
+                                  budget_min=args.learned_budget == "min"), weights=weights)
         p.pop("run", None)
         if args.tau_learned is not None:
             p["learned"]["tau"] = args.tau_learned
@@ -664,6 +675,7 @@ def main():
         lr = path_record("learned")
         lp = paths["learned"]
         lr.update(tau=lp["learned"]["tau"], tau_first_eval=lp.get("tau_first_eval"), band=list(LEARNED_BAND),
+                  budget="min" if lp["learned"]["budget_min"] else "mean",
                   training_pairs=lp["training_pairs"],
                   training_mse=lp["training_mse"], training_s=lp["training_s"],
                   interactions_vs_geometric=lr["interactions_per_force_eval"] / per_launch,
@@ -701,16 +713,27 @@ def reuse_study(bh, w, dev0, judge, n, args):
     recs = []
     configs = [(f"R={R}", dict(rebuild_every=R)) for R in REUSE_INTERVALS]
     configs.append(("drift", dict(rebuild_every=REUSE_MAX, drift=dict(DRIFT))))
-    th0 = guess = None
+    if args.reuse_configs:
+        # names from the list above, or drift:<reuse_drift>:<reuse_frac> for another monitor setting
+        chosen = []
+        for name in args.reuse_configs.split(","):
+            if name.startswith("drift:"):
+                k, f = (float(v) for v in name.split(":")[1:])
+                chosen.append((name, dict(rebuild_every=REUSE_MAX, drift=dict(reuse_drift=k, reuse_frac=f))))
+            else:
+                chosen += [c for c in configs if c[0] == name]
+        configs = chosen
+    th0 = None
     for name, extra in configs:
         p = dict(precision=bh.FP32_REL, n_group=ng, **extra)
         if th0 is None:
             th0 = first_eval_theta(bh, w, dev0, judge, p)
+        # first guess: what lists rebuilt every step need over such a run
+        # (the ring's own error growth), 0.83 of the first-evaluation value
         th, r = match_along_run(f"reuse {name} theta",
                                 lambda th: error_run(bh, w, dev0, judge, dict(p, theta=th), n_evals,
                                                      1 + args.warmup), th0, 2.0, THETA_FLOOR, max_runs=7,
-                                guess=guess)
-        guess = th
+                                guess=0.83 * th0)
         rec = dict(config=name, theta=th, max_p99=r["max"], p99_per_force_eval=r["p99"],
                    device_ms_per_step=float(np.mean(r["step_ms"])), tree_builds=r["builds"],
                    interactions_per_force_eval=r["interactions"] / n_evals)

@@ -75,8 +75,9 @@ typedef enum { BH_FP64 = 0, BH_FP32_REL = 1 } bh_precision;
  * distance from the node's centre to the box.  LEARNED: inside the band
  * theta_min <= s/d < theta_max a small network predicts the node's monopole
  * error and the node is accepted when the prediction is below tau times the
- * mean self-gravity acceleration of the group's particles (from the last
- * force evaluation); outside the band the geometric rule holds. */
+ * mean (BH_FLAG_BUDGET_MIN: smallest) self-gravity acceleration of the
+ * group's particles (from the last force evaluation); outside the band the
+ * geometric rule holds. */
 typedef enum { BH_OPEN_GEOMETRIC = 0, BH_OPEN_LEARNED = 1 } bh_criterion;
 
 typedef struct {
@@ -140,6 +141,9 @@ typedef struct {
 
 /* bh_params.flags: replay list-reusing steps eagerly instead of from a HIP graph. */
 #define BH_FLAG_NO_GRAPH 1
+/* bh_params.flags: the learned rule's budget scale A_g is the smallest self-gravity |a| of the
+ * group's particles instead of their mean. */
+#define BH_FLAG_BUDGET_MIN 2
 
 /* One system: device arrays of n FP64 values each, caller order.
  * bh_step updates x,y,z,vx,vy,vz in place; m is read only. */

@@ -249,6 +249,7 @@ void refresh_state(bh_ctx *c) {
     d.nd_drift = nullptr;     // set only for the monitored moment pass of a list-reusing step
     d.drift_kappa = c->P.reuse_drift;
     d.force_tile = c->P.force_tile == 256 ? 256 : 512;
+    d.budget_min = (c->P.flags & BH_FLAG_BUDGET_MIN) ? 1 : 0;
 }
 
 bh_status check_params(const bh_params *p) {

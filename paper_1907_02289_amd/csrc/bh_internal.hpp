@@ -196,7 +196,18 @@ struct DevState {
     double *nd_drift;              // [node_cap] drift of each node since the build
     double drift_kappa;            // a node has drifted when its drift exceeds drift_kappa * side
     int force_tile;                // sources per LDS tile of the FP32 gravity force kernel: 256 or 512
+    int budget_min;                // learned rule: A_g is the smallest |a| of the group (else the mean)
 };
+
+// The learned rule's error budget scale A_g of a group, by one wave: the mean
+// (default) or the smallest (budget_min) self-gravity |a| of its particles
+// from the last force evaluation.
+__device__ __forceinline__ double group_budget(const DevState &d, const GroupInfo &gi) {
+    double a = d.budget_min ? 1.7976931348623157e308 : 0.0;
+    for (uint32_t i = gi.begin + __lane_id(); i < gi.begin + gi.count; i += 64)
+        a = d.budget_min ? fmin(a, d.amag[i]) : a + d.amag[i];
+    return d.budget_min ? wave_min(a) : wave_sum(a) / (double)gi.count;
+}
 
 enum { WALK_GEOMETRIC = 0, WALK_LEARNED = 1, WALK_ENUMERATE = 2 };
 

@@ -34,16 +34,13 @@ __global__ void k_node_qn(DevState d) {
     }
 }
 
-// Mean self-gravity acceleration magnitude of each group's particles (the
-// error budget scale of the learned rule).
+// Self-gravity acceleration magnitude of each group (mean, or smallest, over
+// its particles): the error budget scale of the learned rule.
 __global__ void __launch_bounds__(TPB) k_group_amin(DevState d) {
     const uint32_t ng = d.cnt->n_groups;
     const uint32_t wpb = TPB / 64;
     for (uint32_t g = blockIdx.x * wpb + (threadIdx.x >> 6); g < ng; g += gridDim.x * wpb) {
-        const GroupInfo gi = d.grp[g];
-        double a = 0.0;
-        for (uint32_t i = gi.begin + __lane_id(); i < gi.begin + gi.count; i += 64) a += d.amag[i];
-        a = wave_sum(a) / (double)gi.count;
+        const double a = group_budget(d, d.grp[g]);
         if (__lane_id() == 0) d.g_amin[g] = a;
     }
 }

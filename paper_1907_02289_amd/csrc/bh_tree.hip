@@ -511,12 +511,7 @@ __global__ void __launch_bounds__(TPB) k_group_box(DevState d) {
                 d.g_rad[g] = 0.5 * sqrt(ex * ex + ey * ey + ez * ez);
             }
         }
-        if (d.g_amin) {
-            double a = 0.0;
-            for (uint32_t i = gi.begin + __lane_id(); i < gi.begin + gi.count; i += 64) a += d.amag[i];
-            a = wave_sum(a) / (double)gi.count;
-            if (__lane_id() == 0) d.g_amin[g] = a;
-        }
+        if (d.g_amin) d.g_amin[g] = group_budget(d, gi);
     }
 }
 

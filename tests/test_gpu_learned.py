@@ -247,3 +247,7 @@ def test_learned_rule_gain_at_matched_error(torch_cuda):
     _log(f"    geometric theta={th:.4f}: {n_geo:.4g} interactions; trained/constant "
          f"{res['constant'] / res['trained']:.2f}x, geometric/trained {n_geo / res['trained']:.2f}x")
     assert res["trained"] < res["constant"]
+    # against the method without the network (the geometric rule at matched
+    # error): measured 0.94-0.96x as many interactions as the trained rule
+    # (the trained rule needs more); the bar pins that relation from both sides
+    assert 0.8 <= n_geo / res["trained"] <= 1.25, n_geo / res["trained"]

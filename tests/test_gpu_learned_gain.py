@@ -14,8 +14,10 @@ On a held-out ring (seed 1), each form is tuned to p99 <= 1e-3 of the
 relative force error against the FP64 direct sum: the learned rule with the
 trained network, the same rule with the network replaced by a constant (the
 training set's mean label), and the geometric rule.  The trained network
-must need fewer interactions than the constant; its ratio to the geometric
-rule is reported.
+must need fewer interactions than the constant; against the geometric rule
+(the method without it) it must stay within 0.8-1.25x of its interaction
+count: on these rings it needs slightly more (about 1.05x), which the test
+pins rather than hides.
 """
 import math
 import sys
@@ -176,3 +178,7 @@ def test_trained_network_beats_a_constant_at_matched_error(torch_cuda):
     _log(f"    geometric theta={th:.4f}: {n_geo:.4g} interactions; constant/trained "
          f"{res['constant'] / res['trained']:.3f}x, geometric/trained {n_geo / res['trained']:.3f}x")
     assert res["trained"] < res["constant"]
+    # against the method without the network (the geometric rule at matched
+    # error): measured 0.94-0.96x as many interactions as the trained rule
+    # (the trained rule needs more); the bar pins that relation from both sides
+    assert 0.8 <= n_geo / res["trained"] <= 1.25, n_geo / res["trained"]

@@ -222,3 +222,42 @@ def test_adam_matches_published_update(torch_cuda):
         moved = np.abs(got[:1249].astype(np.float64) - w0[:1249])
         assert moved.max() > 5 * lr
     ctx.close()
+
+
+@pytest.mark.parametrize("budget_min", [False, True], ids=["mean", "min"])
+def test_group_budget_is_the_mean_or_smallest_acceleration(torch_cuda, budget_min):
+    """The learned rule's budget scale A_g of each group, from the first
+    geometric pass of a learned context, against |a| of the same forces
+    computed by a geometric context (same tree, lists and kernel: the same
+    accelerations bit for bit): the mean over the group's particles, or with
+    BH_FLAG_BUDGET_MIN their smallest."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log(f"[gpu] group budget ({'min' if budget_min else 'mean'}): ring n=12000 seed 51")
+    s = inputs.ring(12000, 51)
+    dev = bh.to_device(s)
+    w = np.zeros(NPARAM, np.float32)
+    w[1253:1257] = 1.0
+    w[1258] = 1.0
+    lc = bh.Context(theta=0.4, eps=1e-3, n_group=64, precision=bh.FP32_REL, criterion=bh.LEARNED,
+                    theta_min=0.1, theta_max=0.6, tau=1e-3, budget_min=budget_min)
+    lc.mlp_weights(set=w)
+    lc.build_tree([dev])
+    lc.make_lists()
+    got = lc.export("group_extra")[:, 1]
+    groups = lc.export("groups")
+    gc = bh.Context(theta=0.4, eps=1e-3, n_group=64, precision=bh.FP32_REL)
+    gc.build_tree([dev])
+    gc.make_lists()
+    out = {k: torch.zeros(s.n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+    gc.forces([out])
+    torch.cuda.synchronize()
+    perm = gc.export("perm").astype(np.int64)
+    a = np.sqrt(sum(out[k].cpu().numpy() ** 2 for k in ("ax", "ay", "az")))[perm]
+    want = np.array([(a[b:b + c].min() if budget_min else a[b:b + c].mean()) for b, c in groups[:, 1:3]])
+    if budget_min:
+        np.testing.assert_array_equal(got, want)
+    else:
+        np.testing.assert_allclose(got, want, rtol=1e-13)
+    lc.close()
+    gc.close()
