@@ -16,10 +16,11 @@ of the run through the last timed one (the 99th percentile, nearest rank, of
 against the library's FP64 direct sum at the same positions).  Each trial
 value is a full untimed run from t = 0; the matched run's per-evaluation
 errors are the ones reported.
-  tuned:   FP32 interactions on group-relative coordinates, group size
-           chosen by measured time per step at matched error, lists reused
-           until the drift monitor asks for a rebuild (at most every 16th
-           step), reuse steps replayed from a HIP graph;
+  tuned:   FP32 interactions on group-relative coordinates; rebuild policy
+           (lists reused until the drift monitor asks for a rebuild, at most
+           every 16th step, or rebuilt every 2 steps), group size and force
+           tile chosen by measured time per step at matched error; reuse
+           steps replayed from a HIP graph;
   plain:   FP64 interactions, groups <= 64, lists rebuilt every step;
   learned: the tuned path with the learned opening rule (network trained
            on the GPU by the library's kernels on separate rings and a
@@ -51,10 +52,12 @@ GROUP_SIZES = (256, 512)
 REUSE_MAX = 16                      # longest list age of the tuned path
 # drift monitor of the tuned path: rebuild when, at some tree level, nodes
 # whose particles moved by more than their side relative to the node's centre
-# of mass since the build hold more than 5% of the particles (on the 16M ring
+# of mass since the build hold more than 10% of the particles (on the 16M ring
 # this keeps the largest p99 along a 101-evaluation run at that of lists
-# rebuilt every step, with half the builds)
-DRIFT = dict(reuse_drift=1.0, reuse_frac=0.05)
+# rebuilt every step, with 39% of the builds)
+DRIFT = dict(reuse_drift=1.0, reuse_frac=0.1)
+# rebuild policies the tuned path chooses from by measured time at matched error
+POLICIES = (("drift monitor", dict(rebuild_every=REUSE_MAX, drift=DRIFT)), ("every 2 steps", dict(rebuild_every=2)))
 LEARNED_BAND = (0.03, 0.5)
 THETA_FLOOR = 0.02
 
@@ -130,22 +133,37 @@ def error_run(bh, w, dev0, judge, p, n_evals, timed_from=None):
     ctx = make_ctx(bh, w, p)
     ctx.step([dev], w.dt, 0, p["rebuild_every"])
     p99, p50, step_ms = [], [], []
-    e = judge.errors(ctx, dev)
-    p99.append(e[0])
-    p50.append(e[1])
+    # per evaluation: force-kernel device time, interactions of the lists
+    # used, group count; walk time of each tree build (evaluation index, ms)
+    force_ms, inter, groups, walk_ms = [], [], [], []
+    builds = 0
+
+    def record(k):
+        nonlocal builds
+        e = judge.errors(ctx, dev)
+        p99.append(e[0])
+        p50.append(e[1])
+        q, st = ctx.query(), ctx.stage_times()
+        force_ms.append(st["forces"])
+        inter.append(q["interactions"])
+        groups.append(q["n_groups"])
+        if q["tree_builds"] > builds:
+            walk_ms.append((k, st["walk"]))
+            builds = q["tree_builds"]
+
+    record(0)
     for k in range(1, n_evals):
         ctx.step_continue(w.dt, 1, p["rebuild_every"])
         if timed_from is not None and k >= timed_from:
             step_ms.append(ctx.stage_times()["step"])
-        e = judge.errors(ctx, dev)
-        p99.append(e[0])
-        p50.append(e[1])
+        record(k)
     q = ctx.query()
     ctx.close()
     del dev
     torch.cuda.empty_cache()
     return dict(p99=p99, p50=p50, max=max(p99), step_ms=step_ms, builds=q["tree_builds"],
-                drift_rebuilds=q["drift_rebuilds"], interactions=q["interactions_evaluated"])
+                drift_rebuilds=q["drift_rebuilds"], interactions=q["interactions_evaluated"],
+                force_ms=force_ms, inter=inter, groups=groups, walk_ms=walk_ms)
 
 
 def first_eval_theta(bh, w, dev0, judge, p, lo=THETA_FLOOR, hi=1.0, iters=10):
@@ -440,6 +458,8 @@ def main():
     ap.add_argument("--legs", default="tuned,plain,learned,collisions,batched",
                     help="comma-separated legs to run (tuned always runs, unless the batched leg runs alone)")
     ap.add_argument("--n-group", type=int, default=None, help="tuned path group size (default: autotuned)")
+    ap.add_argument("--policy", choices=("drift", "every"), default=None,
+                    help="tuned path rebuild policy: the drift monitor or every 2 steps (default: the faster)")
     ap.add_argument("--tile", type=int, default=None, choices=(256, 512),
                     help="tuned path force tile (default: autotuned)")
     ap.add_argument("--theta-tuned", type=float, default=None, help="skip matching, use this theta (tuned path)")
@@ -451,7 +471,7 @@ def main():
                     help="with fixed parameters: skip the untimed runs that report the error along the run")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
     ap.add_argument("--reuse-configs", default=None,
-                    help="reuse study: comma-separated subset of R=1,R=2,R=4,R=8,drift, or drift:<kappa>:<frac>")
+                    help="reuse study: comma-separated subset of R=1,R=2,R=4,R=8,drift, or drift:<kappa>:<frac>[:<cap>]")
     ap.add_argument("--reuse-study", action="store_true",
                     help="only the list-reuse study: fixed rebuild intervals and the drift monitor, each matched "
                          "along the run, and their time per step")
@@ -496,22 +516,38 @@ def main():
     autotune = []
     fixed_run = args.no_error_runs
 
-    # ---- tuned path: theta matched along the run, then the group size and
-    # the force tile by measured time per step at that theta (the error at a
-    # given theta hardly depends on the group size: a changed choice is
-    # checked by a run of its own)
-    base = dict(precision=bh.FP32_REL, n_group=args.n_group or GROUP_SIZES[0], force_tile=512,
-                rebuild_every=REUSE_MAX, drift=dict(DRIFT))
-    r = None
-    if args.theta_tuned is not None:
-        base["theta"] = args.theta_tuned
-    else:
-        th0 = first_eval_theta(bh, w, dev0, judge, base)
-        base["theta_first_eval"] = th0
-        base["theta"], r = match_along_run(
-            f"tuned n_group={base['n_group']} theta",
-            lambda th: error_run(bh, w, dev0, judge, dict(base, theta=th), n_evals, 1 + args.warmup),
-            th0, 2.0, THETA_FLOOR)
+    # ---- tuned path: first the rebuild policy (drift monitor or a fixed
+    # interval), each with its own theta matched along the run, by measured
+    # time per step; then the group size and the force tile by measured time
+    # at that theta (the error at a given theta hardly depends on the group
+    # size: a changed choice is checked by a run of its own)
+    policies = [pl for pl in POLICIES if args.policy in (None, pl[0].split()[0])]
+    base = r = None
+    policy_autotune = []
+    th0 = None
+    for pname, pol in policies:
+        cand = dict(precision=bh.FP32_REL, n_group=args.n_group or GROUP_SIZES[0], force_tile=args.tile or 512,
+                    policy=pname, **{k: (dict(v) if isinstance(v, dict) else v) for k, v in pol.items()})
+        rc = None
+        if args.theta_tuned is not None:
+            cand["theta"] = args.theta_tuned
+        else:
+            if th0 is None:
+                th0 = first_eval_theta(bh, w, dev0, judge, cand)
+            cand["theta_first_eval"] = th0
+            cand["theta"], rc = match_along_run(
+                f"tuned {pname} n_group={cand['n_group']} theta",
+                lambda th: error_run(bh, w, dev0, judge, dict(cand, theta=th), n_evals, 1 + args.warmup),
+                th0, 2.0, THETA_FLOOR, guess=base["theta"] if base else None)
+        if len(policies) > 1:
+            t = timed(bh, w, dev0, cand, args.steps, args.warmup)
+            cost = t["wall"] / args.steps * 1e3
+            policy_autotune.append(dict(policy=pname, theta=cand["theta"], ms_per_step=cost, builds=t["builds"]))
+            log(f"[bench] tuned {pname}: theta={cand['theta']:.5f} {cost:.2f} ms/step, {t['builds']} builds")
+            if base is not None and cost >= base_cost:
+                continue
+            base_cost = cost
+        base, r = cand, rc
     best = None
     sizes = [args.n_group] if args.n_group else list(GROUP_SIZES)
     tiles = [args.tile] if args.tile else [512, 256]
@@ -613,8 +649,8 @@ def main():
                    tree_builds_timed=t["builds"], host_syncs_timed=t["host_syncs"],
                    force_kernel_ms=t["force_ms"] / max(1, t["force_launches"]),
                    dtype="f64" if p["precision"] == bh.FP64 else "f32",
-                   rebuild="every step" if p["rebuild_every"] == 1 else
-                   f"drift monitor {p.get('drift')}, at most every {p['rebuild_every']} steps")
+                   rebuild=(f"drift monitor {p['drift']}, at most every {p['rebuild_every']} steps" if "drift" in p
+                            else f"every {p['rebuild_every']} steps"))
         if "theta_first_eval" in p:
             rec["theta_first_eval"] = p["theta_first_eval"]
         if r is not None:
@@ -638,8 +674,8 @@ def main():
             "workload": workload, "n_particles": n, "eps": w.eps, "dt": w.dt,
             "step": "one kick-drift-kick step (one force evaluation, tree and list builds as they fall)",
             "theta_tuned": tp["theta"], "n_group": tp["n_group"], "force_tile": tp["force_tile"],
-            "rebuild": f"drift monitor {tp['drift']}, "
-            f"at most every {tp['rebuild_every']} steps", "positions_and_integration": "f64",
+            "rebuild": (f"drift monitor {tp['drift']}, at most every {tp['rebuild_every']} steps" if "drift" in tp
+                        else f"every {tp['rebuild_every']} steps"), "positions_and_integration": "f64",
             "matched_error": (f"p99 <= {TARGET_P99} at every one of the {n_evals} force evaluations through the "
                               f"last timed one, for each path; theta bracket floor {THETA_FLOOR}"),
         },
@@ -648,6 +684,7 @@ def main():
         "tree_builds_timed": tu["builds"],
         "tuned": path_record("tuned"),
         "group_size_autotune": autotune,
+        "rebuild_policy_autotune": policy_autotune,
         "force_kernel_ms": avg_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS,
@@ -657,7 +694,8 @@ def main():
                      / FP32_PEAK_TFLOPS},
         "stages_ms_last": tu["stages"],
         "reproduce_without_matching": (f"--steps {args.steps} --warmup {args.warmup} --n-group {tp['n_group']} "
-                                       f"--tile {tp['force_tile']} --theta-tuned {tp['theta']!r}"
+                                       f"--tile {tp['force_tile']} --policy {tp['policy'].split()[0]} "
+                                       f"--theta-tuned {tp['theta']!r}"
                                        + (f" --theta-plain {paths['plain']['theta']!r}" if "plain" in paths else "")
                                        + (f" --tau-learned {paths['learned']['learned']['tau']!r}"
                                           if "learned" in paths else "")),
@@ -718,8 +756,10 @@ def reuse_study(bh, w, dev0, judge, n, args):
         chosen = []
         for name in args.reuse_configs.split(","):
             if name.startswith("drift:"):
-                k, f = (float(v) for v in name.split(":")[1:])
-                chosen.append((name, dict(rebuild_every=REUSE_MAX, drift=dict(reuse_drift=k, reuse_frac=f))))
+                parts = name.split(":")[1:]
+                k, f = float(parts[0]), float(parts[1])
+                cap = int(parts[2]) if len(parts) > 2 else REUSE_MAX
+                chosen.append((name, dict(rebuild_every=cap, drift=dict(reuse_drift=k, reuse_frac=f))))
             else:
                 chosen += [c for c in configs if c[0] == name]
         configs = chosen
@@ -734,11 +774,23 @@ def reuse_study(bh, w, dev0, judge, n, args):
                                 lambda th: error_run(bh, w, dev0, judge, dict(p, theta=th), n_evals,
                                                      1 + args.warmup), th0, 2.0, THETA_FLOOR, max_runs=7,
                                 guess=0.83 * th0)
+        ns = [1e6 * f / max(1, i) for f, i in zip(r["force_ms"], r["inter"])]
         rec = dict(config=name, theta=th, max_p99=r["max"], p99_per_force_eval=r["p99"],
                    device_ms_per_step=float(np.mean(r["step_ms"])), tree_builds=r["builds"],
-                   interactions_per_force_eval=r["interactions"] / n_evals)
+                   interactions_per_force_eval=r["interactions"] / n_evals,
+                   force_ns_per_interaction_per_eval=ns, groups_per_eval=r["groups"],
+                   interactions_per_eval=r["inter"], walk_ms_per_build=r["walk_ms"])
+        # force-kernel efficiency early (the bench's window) and late in the run
+        early = slice(1 + args.warmup, min(n_evals, 1 + args.warmup + 20))
+        late = slice(max(0, n_evals - 20), n_evals)
+        for tag, sl in (("early", early), ("late", late)):
+            rec[f"force_ns_per_interaction_{tag}"] = float(np.median(ns[sl]))
+            rec[f"mean_group_size_{tag}"] = float(n / np.mean(r["groups"][sl]))
+            wk = [m for k, m in r["walk_ms"] if sl.start <= k < sl.stop]
+            rec[f"walk_ms_{tag}"] = float(np.mean(wk)) if wk else None
         log(f"[bench] reuse {name}: theta={th:.5f} max p99={r['max']:.3e} "
-            f"{rec['device_ms_per_step']:.2f} ms/step, {r['builds']} builds")
+            f"{rec['device_ms_per_step']:.2f} ms/step, {r['builds']} builds; force ns/interaction "
+            f"{rec['force_ns_per_interaction_early']:.4f} early, {rec['force_ns_per_interaction_late']:.4f} late")
         recs.append(rec)
     fastest = min(recs, key=lambda r: r["device_ms_per_step"])
     print(json.dumps({"metric": "list-reuse study: device ms/step at p99 <= 1e-3 along the whole run",
