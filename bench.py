@@ -18,7 +18,7 @@ value is a full untimed run from t = 0; the matched run's per-evaluation
 errors are the ones reported.
   tuned:   FP32 interactions on group-relative coordinates; rebuild policy
            (lists reused until the drift monitor asks for a rebuild, at most
-           every 16th step, or rebuilt every 2 steps), group size and force
+           16 or 4 steps, or rebuilt every 2 steps), group size and force
            tile chosen by measured time per step at matched error; reuse
            steps replayed from a HIP graph;
   plain:   FP64 interactions, groups <= 64, lists rebuilt every step;
@@ -56,8 +56,13 @@ REUSE_MAX = 16                      # longest list age of the tuned path
 # this keeps the largest p99 along a 101-evaluation run at that of lists
 # rebuilt every step, with 39% of the builds)
 DRIFT = dict(reuse_drift=1.0, reuse_frac=0.1)
-# rebuild policies the tuned path chooses from by measured time at matched error
-POLICIES = (("drift monitor", dict(rebuild_every=REUSE_MAX, drift=DRIFT)), ("every 2 steps", dict(rebuild_every=2)))
+# rebuild policies the tuned path chooses from by measured time at matched
+# error (name, command-line key, parameters): the monitor guards the error of
+# aged lists, its age cap trades the cost of builds against that of lists
+# built for an older state of the ring
+POLICIES = (("drift monitor, lists at most 16 steps old", "drift16", dict(rebuild_every=REUSE_MAX, drift=DRIFT)),
+            ("drift monitor, lists at most 4 steps old", "drift4", dict(rebuild_every=4, drift=DRIFT)),
+            ("every 2 steps", "every2", dict(rebuild_every=2)))
 LEARNED_BAND = (0.03, 0.5)
 THETA_FLOOR = 0.02
 
@@ -112,7 +117,8 @@ class Judge:
 
 def make_ctx(bh, w, p):
     kw = dict(theta=p["theta"], eps=w.eps, central_mass=w.central_mass, precision=p["precision"],
-              n_group=p["n_group"], cyl_radius=p.get("cyl_radius", 0.0), force_tile=p.get("force_tile", 0))
+              n_group=p["n_group"], cyl_radius=p.get("cyl_radius", 0.0), force_tile=p.get("force_tile", 0),
+              pack_groups=p.get("pack_groups", False))
     kw.update(p.get("drift", {}))
     kw.update(p.get("learned", {}))
     kw.update(p.get("contact", {}))
@@ -458,8 +464,9 @@ def main():
     ap.add_argument("--legs", default="tuned,plain,learned,collisions,batched",
                     help="comma-separated legs to run (tuned always runs, unless the batched leg runs alone)")
     ap.add_argument("--n-group", type=int, default=None, help="tuned path group size (default: autotuned)")
-    ap.add_argument("--policy", choices=("drift", "every"), default=None,
-                    help="tuned path rebuild policy: the drift monitor or every 2 steps (default: the faster)")
+    ap.add_argument("--policy", choices=[pl[1] for pl in POLICIES], default=None,
+                    help="tuned path rebuild policy: the drift monitor with lists at most 16 or 4 steps old, or "
+                         "lists rebuilt every 2 steps (default: the fastest at matched error)")
     ap.add_argument("--tile", type=int, default=None, choices=(256, 512),
                     help="tuned path force tile (default: autotuned)")
     ap.add_argument("--theta-tuned", type=float, default=None, help="skip matching, use this theta (tuned path)")
@@ -471,7 +478,8 @@ def main():
                     help="with fixed parameters: skip the untimed runs that report the error along the run")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
     ap.add_argument("--reuse-configs", default=None,
-                    help="reuse study: comma-separated subset of R=1,R=2,R=4,R=8,drift, or drift:<kappa>:<frac>[:<cap>]")
+                    help="reuse study: comma-separated subset of R=1,R=2,R=4,R=8,drift, or drift:<kappa>:<frac>[:<cap>]; "
+                         "a +pack suffix packs small sibling groups")
     ap.add_argument("--reuse-study", action="store_true",
                     help="only the list-reuse study: fixed rebuild intervals and the drift monitor, each matched "
                          "along the run, and their time per step")
@@ -521,13 +529,13 @@ def main():
     # time per step; then the group size and the force tile by measured time
     # at that theta (the error at a given theta hardly depends on the group
     # size: a changed choice is checked by a run of its own)
-    policies = [pl for pl in POLICIES if args.policy in (None, pl[0].split()[0])]
+    policies = [pl for pl in POLICIES if args.policy in (None, pl[1])]
     base = r = None
     policy_autotune = []
     th0 = None
-    for pname, pol in policies:
+    for pname, pkey, pol in policies:
         cand = dict(precision=bh.FP32_REL, n_group=args.n_group or GROUP_SIZES[0], force_tile=args.tile or 512,
-                    policy=pname, **{k: (dict(v) if isinstance(v, dict) else v) for k, v in pol.items()})
+                    policy=pname, policy_key=pkey, **{k: (dict(v) if isinstance(v, dict) else v) for k, v in pol.items()})
         rc = None
         if args.theta_tuned is not None:
             cand["theta"] = args.theta_tuned
@@ -694,7 +702,7 @@ def main():
                      / FP32_PEAK_TFLOPS},
         "stages_ms_last": tu["stages"],
         "reproduce_without_matching": (f"--steps {args.steps} --warmup {args.warmup} --n-group {tp['n_group']} "
-                                       f"--tile {tp['force_tile']} --policy {tp['policy'].split()[0]} "
+                                       f"--tile {tp['force_tile']} --policy {tp['policy_key']} "
                                        f"--theta-tuned {tp['theta']!r}"
                                        + (f" --theta-plain {paths['plain']['theta']!r}" if "plain" in paths else "")
                                        + (f" --tau-learned {paths['learned']['learned']['tau']!r}"
@@ -753,15 +761,20 @@ def reuse_study(bh, w, dev0, judge, n, args):
     configs.append(("drift", dict(rebuild_every=REUSE_MAX, drift=dict(DRIFT))))
     if args.reuse_configs:
         # names from the list above, or drift:<reuse_drift>:<reuse_frac> for another monitor setting
+        # a "+pack" suffix packs small sibling groups
         chosen = []
         for name in args.reuse_configs.split(","):
-            if name.startswith("drift:"):
-                parts = name.split(":")[1:]
+            base, pack = (name[:-5], True) if name.endswith("+pack") else (name, False)
+            if base.startswith("drift:"):
+                parts = base.split(":")[1:]
                 k, f = float(parts[0]), float(parts[1])
                 cap = int(parts[2]) if len(parts) > 2 else REUSE_MAX
-                chosen.append((name, dict(rebuild_every=cap, drift=dict(reuse_drift=k, reuse_frac=f))))
+                extra = dict(rebuild_every=cap, drift=dict(reuse_drift=k, reuse_frac=f))
             else:
-                chosen += [c for c in configs if c[0] == name]
+                extra = next(dict(c[1]) for c in configs if c[0] == base)
+            if pack:
+                extra["pack_groups"] = True
+            chosen.append((name, extra))
         configs = chosen
     th0 = None
     for name, extra in configs:

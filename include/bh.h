@@ -144,6 +144,15 @@ typedef struct {
 /* bh_params.flags: the learned rule's budget scale A_g is the smallest self-gravity |a| of the
  * group's particles instead of their mean. */
 #define BH_FLAG_BUDGET_MIN 2
+/* bh_params.flags: pack small groups.  Below a node of more than n_group particles, runs of
+ * consecutive children that would each be a group (at most n_group particles, or a leaf) are
+ * merged, left to right, into one group while the merged count stays <= n_group; a child that is
+ * split further, or a leaf of more than n_group coincident particles, ends the run.  A packed
+ * group is a contiguous range of sorted particles inside its parent's cell; its box is the grid
+ * box of its particles as for any group, and bh_export BH_EXPORT_GROUPS reports the run's first
+ * node.  The paper forms its groups from tree nodes (Sec. 4.2, (3d)); packing keeps clumpy
+ * regions, where many nodes hold a few particles each, from producing many tiny groups. */
+#define BH_FLAG_PACK_GROUPS 4
 
 /* One system: device arrays of n FP64 values each, caller order.
  * bh_step updates x,y,z,vx,vy,vz in place; m is read only. */
@@ -186,10 +195,12 @@ typedef enum {
     BH_EXPORT_KEYS = 0,       /* uint64[n_particles]  keys in sorted order */
     BH_EXPORT_PERM = 1,       /* uint32[n_particles]  sorted slot -> caller index within its system */
     BH_EXPORT_NODES = 2,      /* per node, int64[n_nodes][8]: level, system, prefix, begin,
-                                 count, first_child, n_child, is_group */
+                                 count, first_child, n_child, is_group (with packing: first of
+                                 a packed run) */
     BH_EXPORT_MOMENTS = 3,    /* double[n_nodes][4]: com x, y, z, mass */
     BH_EXPORT_GROUPS = 4,     /* per group (ascending first particle), int64[n_groups][4]:
-                                 node, begin, count, system; boxes: bh_export_groups */
+                                 node (the first of a packed run), begin, count, system;
+                                 boxes: bh_export_groups */
     BH_EXPORT_LISTS = 5,      /* CSR: int64 pc_off[n_groups+1], int64 pp_off[n_groups+1],
                                  uint32 pc[n_pc], uint32 pp[n_pp], packed in that order,
                                  each list in ascending node id */

@@ -18,7 +18,7 @@ import numpy as np
 from . import build as _build
 
 __all__ = [
-    "lib", "keys", "sort_perm", "tree", "moments", "groups", "group_boxes",
+    "lib", "keys", "sort_perm", "tree", "moments", "groups", "groups_packed", "group_boxes",
     "lists", "forces", "direct", "central", "bh_accel", "direct_accel",
     "kdk", "node_drift", "n_threads", "BHState", "lg2p", "node_qn", "box_ratio2", "features", "mlp_forward", "lists_learned",
     "label_ratio", "keys_cyl", "atan2", "CYL_PERIOD",
@@ -44,6 +44,8 @@ def lib():
         L.orc_moments.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_groups.argtypes = [P, P, P, i32, i64, P]
         L.orc_groups.restype = i64
+        L.orc_groups_packed.argtypes = [P, P, P, P, i32, i64, P, P, P]
+        L.orc_groups_packed.restype = i64
         L.orc_group_boxes.argtypes = [i64, P, P, P, P, P, P, P, P, P]
         L.orc_lists.argtypes = [i64, P, P, P, P, P, dbl, P, P, P, P]
         L.orc_lists_p.argtypes = [i64, P, P, P, P, P, dbl, i64, P, P, P, P]
@@ -51,8 +53,8 @@ def lib():
         L.orc_keys_cyl.restype = C.c_int
         L.orc_atan2.argtypes = [dbl, dbl]
         L.orc_atan2.restype = dbl
-        L.orc_forces.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, dbl, dbl, P, P, P, dbl, dbl, dbl,
-                                 P, P, P, P, P]
+        L.orc_forces.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, dbl, dbl, P, P, P, dbl, dbl,
+                                 dbl, P, P, P, P, P]
         L.orc_direct.argtypes = [i64, P, P, P, P, dbl, dbl, i64, P, P, P, P, dbl, dbl, dbl, P, P, P, P]
         L.orc_central.argtypes = [i64, P, P, P, dbl, dbl, P, P, P]
         L.orc_threads.restype = C.c_int
@@ -166,6 +168,17 @@ def groups(t, n_grp):
     return g[:ng].copy()
 
 
+def groups_packed(t, n_grp):
+    """Packed groups: (first node, particle begin, particle count) of each."""
+    cap = t["begin"].size
+    g, b, c = (np.zeros(cap, np.uint32) for _ in range(3))
+    ng = lib().orc_groups_packed(_p(t["count"]), _p(t["begin"]), _p(t["first_child"]), _p(t["n_child"]),
+                                 int(n_grp), cap, _p(g), _p(b), _p(c))
+    if ng < 0:
+        raise RuntimeError("oracle groups: capacity exceeded")
+    return g[:ng].copy(), b[:ng].copy(), c[:ng].copy()
+
+
 def group_boxes(gnode, t, skey, xs, ys, zs):
     ng = gnode.size
     gbox = np.zeros((ng, 6), np.int32)
@@ -206,17 +219,23 @@ def _contact_args(contact, vel, n):
     return (_p(v[0]), _p(v[1]), _p(v[2]), rc, kappa, eta), v
 
 
-def forces(gnode, t, xs, ys, zs, ms, mom, pc_off, pc, pp_off, pp, eps, G=1.0, vel=None, contact=None):
-    """Barnes-Hut sums over the lists (arrays in sorted order).  contact =
-    (rc, kappa, eta) adds the collision branch of Eq. (2) for particle
-    sources, with vel = (vx, vy, vz) in sorted order."""
+def forces(gnode, t, xs, ys, zs, ms, mom, pc_off, pc, pp_off, pp, eps, G=1.0, vel=None, contact=None,
+           granges=None):
+    """Barnes-Hut sums over the lists (arrays in sorted order).  The groups
+    are the particle ranges of the nodes gnode, or granges = (begin, count)
+    of each group (packed groups).  contact = (rc, kappa, eta) adds the
+    collision branch of Eq. (2) for particle sources, with vel = (vx, vy,
+    vz) in sorted order."""
     n = xs.size
     ax, ay, az, pot, mag = (np.zeros(n) for _ in range(5))
     xs, ys, zs, ms = _f64(xs), _f64(ys), _f64(zs), _f64(ms)
     cargs, _keep = _contact_args(contact, vel, n)
     pc = np.ascontiguousarray(pc, np.uint32) if pc.size else np.zeros(1, np.uint32)
     pp = np.ascontiguousarray(pp, np.uint32) if pp.size else np.zeros(1, np.uint32)
-    lib().orc_forces(gnode.size, _p(gnode), _p(t["begin"]), _p(t["count"]),
+    if granges is None:
+        granges = (t["begin"][gnode], t["count"][gnode])
+    gbeg, gcnt = (np.ascontiguousarray(a, np.uint32) for a in granges)
+    lib().orc_forces(gbeg.size, _p(gbeg), _p(gcnt), _p(t["begin"]), _p(t["count"]),
                      _p(xs), _p(ys), _p(zs), _p(ms),
                      _p(mom["M"]), _p(mom["cx"]), _p(mom["cy"]), _p(mom["cz"]),
                      _p(pc_off), _p(pc), _p(pp_off), _p(pp), float(eps), float(G), *cargs,
@@ -246,7 +265,7 @@ def central(x, y, z, Mc, G, ax, ay, az):
 class BHState:
     """Tree, groups and lists of one build, kept for list-reusing steps."""
 
-    def __init__(self, x, y, z, m, theta, n_leaf, n_grp, with_q=False, cyl_r=0.0):
+    def __init__(self, x, y, z, m, theta, n_leaf, n_grp, with_q=False, cyl_r=0.0, pack=False):
         if cyl_r > 0.0:
             self.lo, self.S, _, key = keys_cyl(x, y, z, cyl_r)
         else:
@@ -256,8 +275,14 @@ class BHState:
         self.tree = tree(self.skey, n_leaf)
         xs, ys, zs, ms = (np.asarray(a)[self.perm] for a in (x, y, z, m))
         self.mom = moments(self.tree, xs, ys, zs, ms, with_q)
-        self.gnode = groups(self.tree, n_grp)
-        self.gbox, self.gcen = group_boxes(self.gnode, self.tree, self.skey, xs, ys, zs)
+        if pack:
+            self.gnode, self.gbeg, self.gcnt = groups_packed(self.tree, n_grp)
+        else:
+            self.gnode = groups(self.tree, n_grp)
+            self.gbeg, self.gcnt = self.tree["begin"][self.gnode], self.tree["count"][self.gnode]
+        # group boxes from each group's particle range (begin[id], count[id])
+        self.gbox, self.gcen = group_boxes(np.arange(self.gnode.size, dtype=np.uint32),
+                                           dict(begin=self.gbeg, count=self.gcnt), self.skey, xs, ys, zs)
         self.pc_off, self.pc, self.pp_off, self.pp = lists(self.gbox, self.tree, theta,
                                                            CYL_PERIOD if cyl_r > 0.0 else 0)
 
@@ -270,7 +295,8 @@ class BHState:
         xs, ys, zs, ms = (np.asarray(a)[self.perm] for a in (x, y, z, m))
         vs = None if vel is None else tuple(np.asarray(a)[self.perm] for a in vel)
         ax, ay, az, pot, mag = forces(self.gnode, self.tree, xs, ys, zs, ms, self.mom,
-                                      self.pc_off, self.pc, self.pp_off, self.pp, eps, G, vs, contact)
+                                      self.pc_off, self.pc, self.pp_off, self.pp, eps, G, vs, contact,
+                                      granges=(self.gbeg, self.gcnt))
         out = [np.empty_like(ax) for _ in range(5)]
         for o, a in zip(out, (ax, ay, az, pot, mag)):
             o[self.perm] = a
@@ -279,7 +305,7 @@ class BHState:
     def interactions(self):
         """Pairs evaluated: sum over groups of n_g * (particles in pp leaves + pc cells)."""
         cnt = self.tree["count"]
-        ng = cnt[self.gnode].astype(np.int64)
+        ng = self.gcnt.astype(np.int64)
         pp_len = np.add.reduceat(cnt[self.pp].astype(np.int64), self.pp_off[:-1]) if self.pp.size else 0
         pp_len = np.where(np.diff(self.pp_off) > 0, pp_len, 0)
         pc_len = np.diff(self.pc_off)

@@ -356,6 +356,58 @@ int64_t orc_groups(const uint32_t *count, const uint32_t *first_child, const uin
     return groups_rec(0, count, first_child, n_child, n_grp, cap, gnode, 0);
 }
 
+/* ------------------------------------------------------------------ */
+/* Packed groups (an option of this implementation; the paper's groups  */
+/* are tree nodes).  Walking down as above, below a node of more than   */
+/* n_grp particles its children are taken in octant order: a child of   */
+/* at most n_grp particles joins the pack opened by the previous child  */
+/* when the pack's count stays <= n_grp, else it opens a new pack; a    */
+/* child of more than n_grp particles (split further, or a leaf of      */
+/* coincident points, which is a group of its own) closes the open      */
+/* pack.  gnode = first node of each pack, gbeg / gcnt = its particle   */
+/* range.  Returns the group count or -1 if cap is too small.           */
+/* ------------------------------------------------------------------ */
+static int64_t packed_rec(int64_t v, const uint32_t *count, const uint32_t *begin, const uint32_t *first_child,
+                          const uint8_t *n_child, int32_t n_grp, int64_t cap, uint32_t *gnode,
+                          uint32_t *gbeg, uint32_t *gcnt, int64_t ng)
+{
+    if (ng < 0) return ng;
+    if (count[v] <= (uint32_t)n_grp || n_child[v] == 0) {
+        if (ng >= cap) return -1;
+        gnode[ng] = (uint32_t)v;
+        gbeg[ng] = begin[v];
+        gcnt[ng] = count[v];
+        return ng + 1;
+    }
+    int64_t open = -1;                        /* the pack the next small child may join */
+    for (int c = 0; c < n_child[v]; ++c) {
+        const int64_t u = first_child[v] + c;
+        if (count[u] <= (uint32_t)n_grp) {
+            if (open >= 0 && gcnt[open] + count[u] <= (uint32_t)n_grp) {
+                gcnt[open] += count[u];
+                continue;
+            }
+            if (ng >= cap) return -1;
+            gnode[ng] = (uint32_t)u;
+            gbeg[ng] = begin[u];
+            gcnt[ng] = count[u];
+            open = ng++;
+        } else {
+            open = -1;
+            ng = packed_rec(u, count, begin, first_child, n_child, n_grp, cap, gnode, gbeg, gcnt, ng);
+            if (ng < 0) return ng;
+        }
+    }
+    return ng;
+}
+
+int64_t orc_groups_packed(const uint32_t *count, const uint32_t *begin, const uint32_t *first_child,
+                          const uint8_t *n_child, int32_t n_grp, int64_t cap, uint32_t *gnode,
+                          uint32_t *gbeg, uint32_t *gcnt)
+{
+    return packed_rec(0, count, begin, first_child, n_child, n_grp, cap, gnode, gbeg, gcnt, 0);
+}
+
 /* Group box in grid units, half-open [min q, max q + 1), taken from the */
 /* particles' keys; group centre = midpoint of the FP64 bounding box.    */
 void orc_group_boxes(int64_t n_groups, const uint32_t *gnode, const uint32_t *begin,
@@ -588,7 +640,8 @@ static void add_particle(int64_t i, int64_t j, const double *x, const double *y,
     add_term(x[i], y[i], z[i], x[j], y[j], z[j], m[j], eps2, G, acc);
 }
 
-void orc_forces(int64_t n_groups, const uint32_t *gnode, const uint32_t *begin, const uint32_t *count,
+void orc_forces(int64_t n_groups, const uint32_t *gbeg, const uint32_t *gcnt,
+                const uint32_t *begin, const uint32_t *count,
                 const double *x, const double *y, const double *z, const double *m,
                 const double *M, const double *cx, const double *cy, const double *cz,
                 const int64_t *pc_off, const uint32_t *pc_ids,
@@ -601,8 +654,7 @@ void orc_forces(int64_t n_groups, const uint32_t *gnode, const uint32_t *begin, 
     orc_contact C = {rc, kappa, eta, vx, vy, vz};
     #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t g = 0; g < n_groups; ++g) {
-        uint32_t v = gnode[g];
-        for (uint32_t i = begin[v]; i < begin[v] + count[v]; ++i) {
+        for (uint32_t i = gbeg[g]; i < gbeg[g] + gcnt[g]; ++i) {
             double acc[5] = {0, 0, 0, 0, 0};
             for (int64_t k = pp_off[g]; k < pp_off[g + 1]; ++k) {
                 uint32_t leaf = pp_ids[k];

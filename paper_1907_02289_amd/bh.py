@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libbh.so")
 
 BH_OK, BH_EINVAL, BH_ENOMEM, BH_EHIP, BH_ESTATE, BH_ECAPACITY = 0, -1, -2, -3, -4, -5
 FP64, FP32_REL = 0, 1
-FLAG_NO_GRAPH, FLAG_BUDGET_MIN = 1, 2
+FLAG_NO_GRAPH, FLAG_BUDGET_MIN, FLAG_PACK_GROUPS = 1, 2, 4
 GEOMETRIC, LEARNED = 0, 1
 EXPORT = dict(keys=0, perm=1, nodes=2, moments=3, groups=4, lists=5, acc_sorted=6, sorted_pos=7, quad=8,
               node_qn=9, group_extra=10, root_box=11, drift=12)
@@ -139,9 +139,10 @@ class Context:
     def __init__(self, theta=0.5, eps=1e-3, G=1.0, central_mass=0.0, n_leaf=8, n_group=64,
                  precision=FP64, criterion=GEOMETRIC, theta_min=0.2, theta_max=1.0, tau=1e-3,
                  use_graphs=True, r_coll=0.0, kappa=0.0, eta=0.0, cyl_radius=0.0, reuse_drift=0.0,
-                 reuse_frac=0.0, force_tile=0, budget_min=False):
+                 reuse_frac=0.0, force_tile=0, budget_min=False, pack_groups=False):
         self.L = load_library()
-        flags = (0 if use_graphs else FLAG_NO_GRAPH) | (FLAG_BUDGET_MIN if budget_min else 0)
+        flags = ((0 if use_graphs else FLAG_NO_GRAPH) | (FLAG_BUDGET_MIN if budget_min else 0)
+                 | (FLAG_PACK_GROUPS if pack_groups else 0))
         self.params = Params(theta, eps, G, central_mass, n_leaf, n_group, precision, criterion,
                              theta_min, theta_max, tau, flags, r_coll, kappa, eta,
                              cyl_radius, reuse_drift, reuse_frac, force_tile)

@@ -250,6 +250,7 @@ void refresh_state(bh_ctx *c) {
     d.drift_kappa = c->P.reuse_drift;
     d.force_tile = c->P.force_tile == 256 ? 256 : 512;
     d.budget_min = (c->P.flags & BH_FLAG_BUDGET_MIN) ? 1 : 0;
+    d.pack_groups = (c->P.flags & BH_FLAG_PACK_GROUPS) ? 1 : 0;
 }
 
 bh_status check_params(const bh_params *p) {
@@ -743,10 +744,10 @@ bh_status bh_set_params(bh_ctx *c, const bh_params *p) {
     if (!c) return BH_EINVAL;
     if (check_params(p) != BH_OK) return fail(c, BH_EINVAL, "invalid parameters");
     int ng = p->n_group > 0 ? p->n_group : 64;
-    // the tree depends on the leaf and group sizes, on the criterion (second
-    // moments) and on the coordinates it is built in
+    // the tree depends on the leaf and group sizes (and group packing), on the
+    // criterion (second moments) and on the coordinates it is built in
     if (ng != c->n_grp_used || p->n_leaf != c->P.n_leaf || p->criterion != c->P.criterion ||
-        p->cyl_radius != c->P.cyl_radius)
+        p->cyl_radius != c->P.cyl_radius || ((p->flags ^ c->P.flags) & BH_FLAG_PACK_GROUPS))
         c->tree_valid = false;
     // switching the drift monitor on needs a build snapshot: the tree is rebuilt first
     if (p->reuse_drift > 0.0 && !(c->P.reuse_drift > 0.0)) c->tree_valid = false;

@@ -197,6 +197,7 @@ struct DevState {
     double drift_kappa;            // a node has drifted when its drift exceeds drift_kappa * side
     int force_tile;                // sources per LDS tile of the FP32 gravity force kernel: 256 or 512
     int budget_min;                // learned rule: A_g is the smallest |a| of the group (else the mean)
+    int pack_groups;               // groups are packs of consecutive small siblings (else single nodes)
 };
 
 // The learned rule's error budget scale A_g of a group, by one wave: the mean

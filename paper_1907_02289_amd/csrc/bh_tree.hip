@@ -433,7 +433,10 @@ __global__ void k_moments_level(DevState d, int l) {
 // Group flags for the current n_grp on an existing tree: a root is a group
 // when small enough or a leaf; a child is a group when its parent is larger
 // than n_grp and the child is small enough or a leaf (each node has exactly
-// one parent, so the writes do not collide).
+// one parent, so the writes do not collide).  With packing, the flag marks
+// the first node of each pack: the parent's thread walks its children in
+// order and starts a new pack where the next small child no longer fits
+// (the pack's particle count is taken later from the next group's start).
 __global__ void k_regroup(DevState d) {
     const uint32_t nn = d.cnt->lvl_off[BH_NLEVELS];
     const uint32_t G = (uint32_t)d.n_grp;
@@ -445,10 +448,21 @@ __global__ void k_regroup(DevState d) {
             d.nd_meta[v] = make_meta(meta_level(meta), nch, grp ? 1u : 0u, meta_sys(meta));
         }
         const uint32_t f = d.nd_first[v];
+        uint32_t run = 0;    // particles in the open pack, 0 when none is open
         for (uint32_t k = 0; k < nch; ++k) {
             const uint32_t u = f + k;
-            const uint32_t mu = d.nd_meta[u];
-            const bool grp = c > G && (d.nd_count[u] <= G || meta_nch(mu) == 0);
+            const uint32_t mu = d.nd_meta[u], cu = d.nd_count[u];
+            bool grp = c > G && (cu <= G || meta_nch(mu) == 0);
+            if (d.pack_groups && grp && cu <= G) {
+                if (run > 0 && run + cu <= G) {
+                    grp = false;             // joins the open pack
+                    run += cu;
+                } else {
+                    run = cu;                // opens a pack
+                }
+            } else {
+                run = 0;                     // a split child or an over-full leaf ends the run
+            }
             d.nd_meta[u] = make_meta(meta_level(mu), meta_nch(mu), grp ? 1u : 0u, meta_sys(mu));
         }
     }
@@ -470,6 +484,17 @@ __global__ void k_group_emit(DevState d) {
         uint32_t b = d.nd_begin[v];
         uint32_t g = d.gmark[b];
         d.grp[g] = GroupInfo{v, b, d.nd_count[v], meta_sys(meta)};
+    }
+}
+
+// Packed groups: the groups partition the sorted particles in order, so a
+// group ends where the next one starts.
+__global__ void k_group_count(DevState d) {
+    const uint32_t ng = d.cnt->n_groups;
+    uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += stride) {
+        const uint32_t end = g + 1 < ng ? d.grp[g + 1].begin : (uint32_t)d.n;
+        d.grp[g].count = end - d.grp[g].begin;
     }
 }
 
@@ -581,10 +606,12 @@ void regroup(const DevState &d, hipStream_t s) {
 
 void make_groups(const DevState &d, hipStream_t s) {
     const unsigned g = grid_for(d.node_cap, 4096);
+    if (d.pack_groups) k_regroup<<<g, TPB, 0, s>>>(d);
     fill_u32(d.gmark, 0u, d.n, s);
     k_group_mark<<<g, TPB, 0, s>>>(d);
     scan_u32(d.gmark, d.gmark, nullptr, d.n, &d.cnt->n_groups, d.scan_tmp, s);
     k_group_emit<<<g, TPB, 0, s>>>(d);
+    if (d.pack_groups) k_group_count<<<grid_for(d.n, 4096), TPB, 0, s>>>(d);
     k_group_box<<<grid_for((size_t)d.n * 64 / 8, 8192), TPB, 0, s>>>(d);
 }
 
