@@ -48,7 +48,10 @@ PAPER_FLOPS_PER_INTERACTION = 31    # the paper's count for a particle-cell inte
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 TARGET_P99 = 1e-3
-GROUP_SIZES = (256, 512)
+# group configurations of the tuned path (group size, packed small siblings),
+# each matched along the run and timed; the first is the one the rebuild
+# policy is chosen on
+GROUP_CONFIGS = ((384, True), (256, True), (512, True), (256, False), (384, False), (512, False))
 REUSE_MAX = 16                      # longest list age of the tuned path
 # drift monitor of the tuned path: rebuild when, at some tree level, nodes
 # whose particles moved by more than their side relative to the node's centre
@@ -464,6 +467,8 @@ def main():
     ap.add_argument("--legs", default="tuned,plain,learned,collisions,batched",
                     help="comma-separated legs to run (tuned always runs, unless the batched leg runs alone)")
     ap.add_argument("--n-group", type=int, default=None, help="tuned path group size (default: autotuned)")
+    ap.add_argument("--pack", choices=("on", "off"), default=None,
+                    help="tuned path: pack small sibling groups (default: autotuned)")
     ap.add_argument("--policy", choices=[pl[1] for pl in POLICIES], default=None,
                     help="tuned path rebuild policy: the drift monitor with lists at most 16 or 4 steps old, or "
                          "lists rebuilt every 2 steps (default: the fastest at matched error)")
@@ -526,16 +531,22 @@ def main():
 
     # ---- tuned path: first the rebuild policy (drift monitor or a fixed
     # interval), each with its own theta matched along the run, by measured
-    # time per step; then the group size and the force tile by measured time
-    # at that theta (the error at a given theta hardly depends on the group
-    # size: a changed choice is checked by a run of its own)
+    # time per step; then the group configuration (size, packing), each
+    # matched along the run (the error at a given theta moves with the group
+    # boxes) and timed; last the force tile, a changed choice checked by an
+    # error run of its own
+    gcands = [(ng, pk) for ng, pk in GROUP_CONFIGS
+              if args.n_group in (None, ng) and args.pack in (None, "on" if pk else "off")]
+    if not gcands:
+        gcands = [(args.n_group, args.pack == "on")]
     policies = [pl for pl in POLICIES if args.policy in (None, pl[1])]
     base = r = None
     policy_autotune = []
     th0 = None
     for pname, pkey, pol in policies:
-        cand = dict(precision=bh.FP32_REL, n_group=args.n_group or GROUP_SIZES[0], force_tile=args.tile or 512,
-                    policy=pname, policy_key=pkey, **{k: (dict(v) if isinstance(v, dict) else v) for k, v in pol.items()})
+        cand = dict(precision=bh.FP32_REL, n_group=gcands[0][0], pack_groups=gcands[0][1],
+                    force_tile=args.tile or 512, policy=pname, policy_key=pkey,
+                    **{k: (dict(v) if isinstance(v, dict) else v) for k, v in pol.items()})
         rc = None
         if args.theta_tuned is not None:
             cand["theta"] = args.theta_tuned
@@ -557,24 +568,39 @@ def main():
             base_cost = cost
         base, r = cand, rc
     best = None
-    sizes = [args.n_group] if args.n_group else list(GROUP_SIZES)
-    tiles = [args.tile] if args.tile else [512, 256]
-    cands = [(ng, tile) for ng in sizes for tile in tiles]
-    for ng, tile in cands if len(cands) > 1 else []:
-        p = dict(base, n_group=ng, force_tile=tile)
+    for ng, pk in gcands if len(gcands) > 1 else []:
+        p = dict(base, n_group=ng, pack_groups=pk)
+        rp = r if (ng, pk) == (base["n_group"], base["pack_groups"]) else None
+        if rp is None and args.theta_tuned is None:
+            p["theta"], rp = match_along_run(
+                f"tuned n_group={ng}{' packed' if pk else ''} theta",
+                lambda th: error_run(bh, w, dev0, judge, dict(p, theta=th), n_evals, 1 + args.warmup),
+                base["theta_first_eval"], 2.0, THETA_FLOOR, guess=base["theta"])
         t = timed(bh, w, dev0, p, args.steps, args.warmup)
         cost = t["wall"] / args.steps * 1e3
-        autotune.append(dict(n_group=ng, force_tile=tile, theta=p["theta"], ms_per_step=cost))
-        log(f"[bench] tuned n_group={ng} tile={tile}: {cost:.2f} ms/step")
+        autotune.append(dict(n_group=ng, pack_groups=pk, force_tile=p["force_tile"], theta=p["theta"],
+                             ms_per_step=cost, max_p99=rp["max"] if rp else None))
+        log(f"[bench] tuned n_group={ng}{' packed' if pk else ''} theta={p['theta']:.5f}: {cost:.2f} ms/step")
         if best is None or cost < best[0]:
-            best = (cost, p)
-    p = best[1] if best else dict(base, n_group=cands[0][0], force_tile=cands[0][1])
-    if r is None or (p["n_group"], p["force_tile"]) != (base["n_group"], base["force_tile"]):
+            best = (cost, p, rp)
+    if best is not None:
+        _, base, r = best
+    p = base
+    if not args.tile:
+        q = dict(p, force_tile=256 if p["force_tile"] == 512 else 512)
+        t0 = best[0] if best else timed(bh, w, dev0, p, args.steps, args.warmup)["wall"] / args.steps * 1e3
+        t = timed(bh, w, dev0, q, args.steps, args.warmup)
+        cost = t["wall"] / args.steps * 1e3
+        autotune.append(dict(n_group=q["n_group"], pack_groups=q["pack_groups"], force_tile=q["force_tile"],
+                             theta=q["theta"], ms_per_step=cost, max_p99=None))
+        log(f"[bench] tuned tile={q['force_tile']}: {cost:.2f} ms/step (tile {p['force_tile']}: {t0:.2f})")
+        if cost < t0:
+            p = q
+    if r is None or p is not base:
         if not fixed_run:
             r2 = error_run(bh, w, dev0, judge, p, n_evals, 1 + args.warmup)
             if r is not None and r2["max"] > TARGET_P99:
-                log(f"[bench] n_group={p['n_group']} tile={p['force_tile']}: max p99 {r2['max']:.3e} misses; "
-                    f"keeping n_group={base['n_group']} tile={base['force_tile']}")
+                log(f"[bench] tile={p['force_tile']}: max p99 {r2['max']:.3e} misses; keeping tile {base['force_tile']}")
                 p = base
             else:
                 r = r2
@@ -650,7 +676,8 @@ def main():
 
     def path_record(name):
         p, r, t = paths[name], paths[name]["run"], res[name]
-        rec = dict(theta=p["theta"], n_group=p["n_group"], force_tile=p.get("force_tile", 512),
+        rec = dict(theta=p["theta"], n_group=p["n_group"], pack_groups=p.get("pack_groups", False),
+                   force_tile=p.get("force_tile", 512),
                    s_per_step=t["wall"] / args.steps,
                    interactions_per_s=t["interactions"] / t["wall"],
                    interactions_per_force_eval=t["interactions"] / max(1, t["force_evals"]),
@@ -681,7 +708,8 @@ def main():
         "config": {
             "workload": workload, "n_particles": n, "eps": w.eps, "dt": w.dt,
             "step": "one kick-drift-kick step (one force evaluation, tree and list builds as they fall)",
-            "theta_tuned": tp["theta"], "n_group": tp["n_group"], "force_tile": tp["force_tile"],
+            "theta_tuned": tp["theta"], "n_group": tp["n_group"], "pack_groups": tp["pack_groups"],
+            "force_tile": tp["force_tile"],
             "rebuild": (f"drift monitor {tp['drift']}, at most every {tp['rebuild_every']} steps" if "drift" in tp
                         else f"every {tp['rebuild_every']} steps"), "positions_and_integration": "f64",
             "matched_error": (f"p99 <= {TARGET_P99} at every one of the {n_evals} force evaluations through the "
@@ -702,6 +730,7 @@ def main():
                      / FP32_PEAK_TFLOPS},
         "stages_ms_last": tu["stages"],
         "reproduce_without_matching": (f"--steps {args.steps} --warmup {args.warmup} --n-group {tp['n_group']} "
+                                       f"--pack {'on' if tp['pack_groups'] else 'off'} "
                                        f"--tile {tp['force_tile']} --policy {tp['policy_key']} "
                                        f"--theta-tuned {tp['theta']!r}"
                                        + (f" --theta-plain {paths['plain']['theta']!r}" if "plain" in paths else "")
