@@ -325,7 +325,7 @@ def direct_accel(x, y, z, m, eps, G=1.0, vel=None, contact=None):
 
 def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
         theta=None, n_leaf=8, n_grp=64, rebuild_every=1, contact=None, trace=None, cyl_r=0.0,
-        rebuild_at=None):
+        rebuild_at=None, pack=False):
     """Kick-drift-kick leapfrog in FP64 (the integration step (4) of Sec. 4.2).
 
     theta=None uses the direct sum; otherwise Barnes-Hut with lists rebuilt
@@ -336,7 +336,7 @@ def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
     drift.  cyl_r > 0 builds the trees on cylindrical coordinates around
     that radius.  rebuild_at, if given, replaces rebuild_every: the set of
     force evaluations (0 = the first, k = the one ending step k) before which
-    the tree and lists are built.  trace, if given, is called as
+    the tree and lists are built.  pack packs small sibling groups.  trace, if given, is called as
     trace(step, x, y, z, vx, vy, vz) after every completed step.  Returns new
     copies of (x, y, z, vx, vy, vz).
     """
@@ -352,7 +352,7 @@ def kdk(x, y, z, vx, vy, vz, m, dt, n_steps, eps, G=1.0, central_mass=0.0,
         else:
             build = step % rebuild_every == 0 if rebuild_at is None else step in rebuild_at
             if state is None or build:
-                state = BHState(x, y, z, m, theta, n_leaf, n_grp, cyl_r=cyl_r)
+                state = BHState(x, y, z, m, theta, n_leaf, n_grp, cyl_r=cyl_r, pack=pack)
             else:
                 state.refresh(x, y, z, m)
             ax, ay, az, _, _ = state.accel(x, y, z, m, eps, G, vel, contact)

@@ -7,13 +7,16 @@ synthetic features, and the learned walk with fixed weights.
 - gradient of the mean squared error: within 1e-4 of the FP64 oracle
   gradient (itself pinned by finite differences on the CPU), for full and
   ragged batches;
-- learned walk: lists bit-exact against the oracle walking with the GPU's
-  moments, node features, group data and the same weights.
+- learned walk: lists bit-exact against the oracle walking over its own
+  tree, moments, node features and group data with the same weights, for
+  tree-node and packed groups.
 """
 import sys
 
 import numpy as np
 import pytest
+
+from learned_ref import learned_inputs
 
 import oracle
 from oracle import mlp
@@ -88,39 +91,37 @@ def test_network_gradient_matches_fp64(torch_cuda, batch):
     ctx.close()
 
 
-def test_learned_walk_with_fixed_weights(torch_cuda):
+@pytest.mark.parametrize("pack", [False, True], ids=["tree_groups", "packed_groups"])
+def test_learned_walk_with_fixed_weights(torch_cuda, pack):
     """Lists of the learned rule (band theta_min..theta_max, error budget tau)
-    with hand-set weights: bit-exact against the oracle's learned walk."""
+    with hand-set weights: bit-exact against the oracle's learned walk over
+    the oracle's own tree, moments, second-moment norms, groups and budgets.
+    The context runs its geometric budget pass in FP64, so both budgets are
+    FP64 sums of the same terms and agree to rounding, far inside anything
+    that moves a decision."""
     torch = torch_cuda
     from paper_1907_02289_amd import bh
-    _log("[gpu] learned walk, fixed weights")
+    n_grp = 384 if pack else 64
+    _log(f"[gpu] learned walk, fixed weights, ring n=20000 seed 51, groups <= {n_grp}{' packed' if pack else ''}")
     s = inputs.ring(20000, 51)
     X, Y = _synthetic(4096, 5)
     w = _weights(X, Y, 6)
-    ctx = bh.Context(theta=0.3, eps=1e-3, n_group=64, precision=bh.FP32_REL, criterion=bh.LEARNED,
-                     theta_min=0.05, theta_max=0.6, tau=3e-3)
+    ctx = bh.Context(theta=0.3, eps=1e-3, n_group=n_grp, precision=bh.FP64, criterion=bh.LEARNED,
+                     theta_min=0.05, theta_max=0.6, tau=3e-3, pack_groups=pack)
     ctx.mlp_weights(set=w)
     ctx.build_tree([bh.to_device(s)])
     ctx.make_lists()
     torch.cuda.synchronize()
-    nodes = ctx.export("nodes")
-    t = dict(level=nodes[:, 0].astype(np.uint8), prefix=nodes[:, 2].astype(np.uint64),
-             begin=nodes[:, 3].astype(np.uint32), count=nodes[:, 4].astype(np.uint32),
-             first_child=nodes[:, 5].astype(np.uint32), n_child=nodes[:, 6].astype(np.uint8))
-    mom = ctx.export("moments")
-    qn = ctx.export("node_qn")
-    gbox, gcen = ctx.export_groups()
-    extra = ctx.export("group_extra")
-    S = 2.0 ** 21 / ctx.export("root_box")[0, 3]
-    want = oracle.lists_learned(gbox, gcen, extra[:, 0], extra[:, 1], t, mom, qn, w, S, theta=0.3,
-                                theta_min=0.05, theta_max=0.6, tau=3e-3)
+    st, L = learned_inputs(s, 0.3, 1e-3, n_grp, pack=pack)
+    want = oracle.lists_learned(L["gbox"], L["gcen"], L["grad"], L["gamin"], L["t"], L["com4"], L["qn"], w,
+                                L["S"], theta=0.3, theta_min=0.05, theta_max=0.6, tau=3e-3)
     got = ctx.export("lists")
     for a, b in zip(got, want):
         np.testing.assert_array_equal(a, b)
     # the network did decide something inside the band: the lists differ from
     # both geometric limits
-    lo = oracle.lists(gbox, t, 0.05)
-    hi = oracle.lists(gbox, t, 0.6)
+    lo = oracle.lists(L["gbox"], L["t"], 0.05)
+    hi = oracle.lists(L["gbox"], L["t"], 0.6)
     assert got[1].size != lo[1].size and got[1].size != hi[1].size
     _log(f"    node-list entries: theta_max {hi[1].size}, learned {got[1].size}, theta_min {lo[1].size}")
     ctx.close()

@@ -7,6 +7,7 @@ group boxes, centres and lists bit-exact; FP64 forces within 1e-12 of the sum
 of the terms' magnitudes; FP32 within the FP32 bars of the oracle on the same
 lists.
 """
+import math
 import sys
 
 import numpy as np
@@ -174,4 +175,76 @@ def test_packed_batched_systems(torch_cuda):
         g = {q: v.cpu().numpy() for q, v in outs[k].items()}
         err = np.sqrt((g["ax"] - ax) ** 2 + (g["ay"] - ay) ** 2 + (g["az"] - az) ** 2)
         assert np.all(err <= 1e-12 * mag)
+    ctx.close()
+
+
+def _contact_params(t_c, e):
+    """Spring and dashpot of a contact lasting t_c with restitution e."""
+    wd = math.pi / t_c
+    gamma = -math.log(e) / t_c
+    return wd * wd + gamma * gamma, 2.0 * gamma
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_packed_groups_with_contacts(torch_cuda, precision):
+    """The collision branch of Eq. (2) over packed groups of <= 384 (the
+    bench's tuned configuration) against the oracle on the same packs."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log(f"[gpu] packed groups with contacts, ring n=20000 seed 31, precision {precision}")
+    s = inputs.ring(20000, 31, v_disp=3e-3)
+    theta, eps, n_grp, rc = 0.5, 1e-4, 384, 2e-3
+    kappa, eta = _contact_params(0.02, 0.5)
+    ctx = bh.Context(theta=theta, eps=eps, n_group=n_grp, precision=precision, r_coll=rc, kappa=kappa, eta=eta,
+                     pack_groups=True)
+    ctx.build_tree([bh.to_device(s)])
+    ctx.make_lists()
+    out = {k: torch.zeros(s.n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+    ctx.forces([out])
+    torch.cuda.synchronize()
+    st = oracle.BHState(s.x, s.y, s.z, s.m, theta, 8, n_grp, pack=True)
+    _compare(ctx, st)
+    ax, ay, az, _, mag = st.accel(s.x, s.y, s.z, s.m, eps, vel=(s.vx, s.vy, s.vz), contact=(rc, kappa, eta))
+    nx, ny, nz, _, _ = st.accel(s.x, s.y, s.z, s.m, eps)
+    moved = np.sqrt((nx - ax) ** 2 + (ny - ay) ** 2 + (nz - az) ** 2) > 1e-3 * mag
+    assert moved.sum() > 50                       # the contact terms matter
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    err = np.sqrt((g["ax"] - ax) ** 2 + (g["ay"] - ay) ** 2 + (g["az"] - az) ** 2)
+    if precision == 0:
+        assert np.all(err <= 1e-12 * mag), f"max err/mag {np.max(err / mag)}"
+    else:
+        rel = err / np.sqrt(ax ** 2 + ay ** 2 + az ** 2)
+        _log(f"    fp32 rel err: median {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e} max {rel.max():.2e}")
+        fp32_bars(rel, "packed groups with contacts")
+    ctx.close()
+
+
+def test_packed_monitor_trajectory_matches_oracle(torch_cuda):
+    """FP64 leapfrog over packed groups with the drift monitor choosing the
+    rebuilds (lists at most 4 steps old, as in the bench's tuned
+    configuration): the trajectory equals the oracle's with packed groups
+    rebuilt before the same steps."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log("[gpu] packed groups, drift monitor trajectory: ring n=3000 seed 33, fp64, 12 steps of dt 2e-3")
+    s = inputs.ring(3000, 33, central_mass=1.0, v_disp=3e-3)
+    dt, n, cap = 2e-3, 12, 4
+    dev = bh.to_device(s)
+    ctx = bh.Context(theta=0.5, eps=1e-3, central_mass=1.0, n_group=128, precision=bh.FP64, reuse_drift=0.1,
+                     reuse_frac=0.02, pack_groups=True)
+    ctx.step([dev], dt, 0, cap)
+    builds = []
+    for k in range(n):
+        b0 = ctx.query()["tree_builds"]
+        ctx.step_continue(dt, 1, cap)
+        if ctx.query()["tree_builds"] > b0:
+            builds.append(k + 1)
+    torch.cuda.synchronize()
+    q = ctx.query()
+    _log(f"    rebuilt before steps {builds} ({q['drift_rebuilds']} by the monitor)")
+    assert 0 < q["drift_rebuilds"] and len(builds) < n
+    ref = oracle.kdk(s.x, s.y, s.z, s.vx, s.vy, s.vz, s.m, dt, n, 1e-3, central_mass=1.0, theta=0.5,
+                     n_grp=128, rebuild_at=set([0] + builds), pack=True)
+    for k, f in enumerate(("x", "y", "z", "vx", "vy", "vz")):
+        assert np.max(np.abs(dev[f].cpu().numpy() - ref[k])) < 1e-10, f
     ctx.close()
