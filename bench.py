@@ -248,7 +248,8 @@ def match_along_run(name, run, x0, alpha, floor, max_runs=6, tol=0.015, guess=No
     """Largest x <= x0 (theta, or the learned rule's tau) whose run keeps
     p99 <= 1e-3 at every evaluation; the error grows with x.  Starts at
     `guess` (default x0); secant steps on log(max p99) against log(x), a
-    power law of exponent alpha until two points bracket the target; at most
+    power law of exponent alpha (or, after two misses, of the slope between
+    them) until two points bracket the target; at most
     max_runs runs.  Returns (x, run record); raises when no trial down to the
     floor meets the target."""
     seen = {}
@@ -277,7 +278,13 @@ def match_along_run(name, run, x0, alpha, floor, max_runs=6, tol=0.015, guess=No
                 break
             x = xn
         else:
-            xn = bad * (0.97 * TARGET_P99 / seen[bad]["max"]) ** (1.0 / alpha)
+            # only misses so far: the power law through the two smallest
+            # misses once there are two, else the assumed exponent
+            slope = alpha
+            miss = sorted(seen)[:2]
+            if len(miss) == 2 and seen[miss[1]]["max"] > seen[miss[0]]["max"]:
+                slope = max(0.25, math.log(seen[miss[1]]["max"] / seen[miss[0]]["max"]) / math.log(miss[1] / miss[0]))
+            xn = bad * (0.97 * TARGET_P99 / seen[bad]["max"]) ** (1.0 / slope)
             if xn <= floor:
                 if bad <= floor:
                     raise RuntimeError(f"{name}: p99 {seen[bad]['max']:.3e} > {TARGET_P99} at the floor {floor}")
@@ -487,7 +494,7 @@ def main():
                     help="with fixed parameters: skip the untimed runs that report the error along the run")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
     ap.add_argument("--reuse-configs", default=None,
-                    help="reuse study: comma-separated subset of R=1,R=2,R=4,R=8,drift, or drift:<kappa>:<frac>[:<cap>]; "
+                    help="reuse study: comma-separated subset of R=1,R=2,R=4,R=8,R=16,drift, or drift:<kappa>:<frac>[:<cap>]; "
                          "a +pack suffix packs small sibling groups")
     ap.add_argument("--reuse-study", action="store_true",
                     help="only the list-reuse study: fixed rebuild intervals and the drift monitor, each matched "
@@ -779,7 +786,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-REUSE_INTERVALS = (1, 2, 4, 8)
+REUSE_INTERVALS = (1, 2, 4, 8, 16)
 
 
 def reuse_study(bh, w, dev0, judge, n, args):
@@ -816,10 +823,16 @@ def reuse_study(bh, w, dev0, judge, n, args):
             th0 = first_eval_theta(bh, w, dev0, judge, p)
         # first guess: what lists rebuilt every step need over such a run
         # (the ring's own error growth), 0.83 of the first-evaluation value
-        th, r = match_along_run(f"reuse {name} theta",
-                                lambda th: error_run(bh, w, dev0, judge, dict(p, theta=th), n_evals,
-                                                     1 + args.warmup), th0, 2.0, THETA_FLOOR, max_runs=7,
-                                guess=0.83 * th0)
+        try:
+            th, r = match_along_run(f"reuse {name} theta",
+                                    lambda th: error_run(bh, w, dev0, judge, dict(p, theta=th), n_evals,
+                                                         1 + args.warmup), th0, 2.0, THETA_FLOOR, max_runs=7,
+                                    guess=0.83 * th0)
+        except RuntimeError as e:
+            # no theta down to the floor holds the target along this run
+            log(f"[bench] reuse {name}: {e}")
+            recs.append(dict(config=name, theta=None, unmatched=str(e)))
+            continue
         ns = [1e6 * f / max(1, i) for f, i in zip(r["force_ms"], r["inter"])]
         rec = dict(config=name, theta=th, max_p99=r["max"], p99_per_force_eval=r["p99"],
                    device_ms_per_step=float(np.mean(r["step_ms"])), tree_builds=r["builds"],
@@ -835,10 +848,12 @@ def reuse_study(bh, w, dev0, judge, n, args):
             wk = [m for k, m in r["walk_ms"] if sl.start <= k < sl.stop]
             rec[f"walk_ms_{tag}"] = float(np.mean(wk)) if wk else None
         log(f"[bench] reuse {name}: theta={th:.5f} max p99={r['max']:.3e} "
-            f"{rec['device_ms_per_step']:.2f} ms/step, {r['builds']} builds; force ns/interaction "
-            f"{rec['force_ns_per_interaction_early']:.4f} early, {rec['force_ns_per_interaction_late']:.4f} late")
+            f"{rec['device_ms_per_step']:.2f} ms/step, {r['builds']} builds; force ps/interaction "
+            f"{1e3 * rec['force_ns_per_interaction_early']:.4f} early, "
+            f"{1e3 * rec['force_ns_per_interaction_late']:.4f} late")
         recs.append(rec)
-    fastest = min(recs, key=lambda r: r["device_ms_per_step"])
+    fastest = min((r for r in recs if r["theta"] is not None), key=lambda r: r["device_ms_per_step"],
+                  default=dict(config=None))
     print(json.dumps({"metric": "list-reuse study: device ms/step at p99 <= 1e-3 along the whole run",
                       "config": {"workload": f"ring{n}", "n_group": ng, "eps": w.eps, "dt": w.dt,
                                  "force_evaluations": n_evals, "timed_from": 1 + args.warmup},
