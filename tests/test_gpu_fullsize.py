@@ -1,8 +1,9 @@
 """Parity at the full sizes of the workloads, on sampled outputs: the 2^20
 ring (FP32 interactions, groups <= 256) at t = 0 and along 10 steps rebuilt
-every step; the 2^24 ring (the benchmark workload, FP32, groups <= 256,
-theta 0.1035); the 64 batched Plummer spheres (2.2M particles, autotuned
-group size, 20 steps).  Keys, permutation and node arrays are compared in
+every step; the 2^24 ring in the benchmark's launch configuration (FP32,
+packed groups <= 384, 512-source tiles, theta 0.0846, the value matched
+along the benchmark's run); the 64 batched Plummer spheres (2.2M particles,
+autotuned group size, 20 steps).  Keys, permutation and node arrays are compared in
 full; lists and forces for a random sample of groups, against the oracle
 walking those groups and evaluating their lists in FP64."""
 import sys
@@ -35,7 +36,7 @@ def _subset_lists(pc_off, pc, pp_off, pp, sel):
 
 
 def _check(ctx, x, y, z, m, theta, eps, n_grp, n_sample_groups, seed, gx, gy, gz, central_mass=0.0,
-           resorted=False):
+           resorted=False, pack=False):
     """The oracle's full build of (x, y, z, m) against the context's keys,
     permutation, nodes, moments, groups and group boxes; the lists and FP32
     forces of a random sample of groups against the oracle walking those
@@ -65,9 +66,17 @@ def _check(ctx, x, y, z, m, theta, eps, n_grp, n_sample_groups, seed, gx, gy, gz
     np.testing.assert_array_equal(nodes[:, 2].astype(np.uint64), t["prefix"])
     xs, ys, zs, ms = (a[perm] for a in (x, y, z, m))
     mom = oracle.moments(t, xs, ys, zs, ms)
-    g = oracle.groups(t, n_grp)
-    np.testing.assert_array_equal(ctx.export("groups")[:, 0], g)
-    gbox, gcen = oracle.group_boxes(g, t, skey, xs, ys, zs)
+    if pack:
+        g, gbeg, gcnt = oracle.groups_packed(t, n_grp)
+    else:
+        g = oracle.groups(t, n_grp)
+        gbeg, gcnt = t["begin"][g], t["count"][g]
+    groups = ctx.export("groups")
+    np.testing.assert_array_equal(groups[:, 0], g)
+    np.testing.assert_array_equal(groups[:, 1], gbeg)
+    np.testing.assert_array_equal(groups[:, 2], gcnt)
+    gbox, gcen = oracle.group_boxes(np.arange(g.size, dtype=np.uint32), dict(begin=gbeg, count=gcnt), skey,
+                                    xs, ys, zs)
     box, cen = ctx.export_groups()
     np.testing.assert_array_equal(box, gbox)
     np.testing.assert_array_equal(cen, gcen)
@@ -80,10 +89,11 @@ def _check(ctx, x, y, z, m, theta, eps, n_grp, n_sample_groups, seed, gx, gy, gz
     np.testing.assert_array_equal(b, o_pc)
     np.testing.assert_array_equal(c, o_pp_off)
     np.testing.assert_array_equal(d, o_pp)
-    ax, ay, az, _, _ = oracle.forces(g[sel], t, xs, ys, zs, ms, mom, o_pc_off, o_pc, o_pp_off, o_pp, eps)
+    ax, ay, az, _, _ = oracle.forces(g[sel], t, xs, ys, zs, ms, mom, o_pc_off, o_pc, o_pp_off, o_pp, eps,
+                                     granges=(gbeg[sel], gcnt[sel]))
     if central_mass:
         oracle.central(xs, ys, zs, central_mass, 1.0, ax, ay, az)
-    idx = np.concatenate([np.arange(t["begin"][v], t["begin"][v] + t["count"][v]) for v in g[sel]])
+    idx = np.concatenate([np.arange(b, b + c) for b, c in zip(gbeg[sel].astype(np.int64), gcnt[sel].astype(np.int64))])
     rel = np.sqrt((gx[idx] - ax[idx]) ** 2 + (gy[idx] - ay[idx]) ** 2 + (gz[idx] - az[idx]) ** 2) / \
         np.sqrt(ax[idx] ** 2 + ay[idx] ** 2 + az[idx] ** 2)
     _log(f"    {idx.size} particles: fp32 rel err median {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e}")
@@ -91,14 +101,14 @@ def _check(ctx, x, y, z, m, theta, eps, n_grp, n_sample_groups, seed, gx, gy, gz
     return perm, idx
 
 
-def _run(n, seed, theta, eps, n_grp, n_sample_groups, r_out=1.1, z_sigma=1e-3):
+def _run(n, seed, theta, eps, n_grp, n_sample_groups, r_out=1.1, z_sigma=1e-3, pack=False, tile=0):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1907_02289_amd import bh
     s = inputs.ring(n, seed, r_out=r_out, z_sigma=z_sigma, central_mass=1.0)
-    _log(f"[gpu] fullsize n={n} theta={theta}")
-    ctx = bh.Context(theta=theta, eps=eps, n_group=n_grp, precision=bh.FP32_REL)
+    _log(f"[gpu] fullsize n={n} theta={theta} groups <= {n_grp}{' packed' if pack else ''}")
+    ctx = bh.Context(theta=theta, eps=eps, n_group=n_grp, precision=bh.FP32_REL, pack_groups=pack, force_tile=tile)
     dev = bh.to_device(s)
     ctx.build_tree([dev])
     ctx.make_lists()
@@ -107,7 +117,7 @@ def _run(n, seed, theta, eps, n_grp, n_sample_groups, r_out=1.1, z_sigma=1e-3):
     torch.cuda.synchronize()
     perm = ctx.export("perm")
     gx, gy, gz = (out[k].cpu().numpy()[perm] for k in ("ax", "ay", "az"))
-    _check(ctx, s.x, s.y, s.z, s.m, theta, eps, n_grp, n_sample_groups, seed, gx, gy, gz)
+    _check(ctx, s.x, s.y, s.z, s.m, theta, eps, n_grp, n_sample_groups, seed, gx, gy, gz, pack=pack)
     ctx.close()
 
 
@@ -117,7 +127,7 @@ def test_ring_1m_fp32_groups256():
 
 @pytest.mark.slow
 def test_ring_16m_benchmark_configuration():
-    _run(1 << 24, 3, 0.103515625, 1e-4, 256, 48, r_out=1.2, z_sigma=5e-4)
+    _run(1 << 24, 3, 0.08457338666050794, 1e-4, 384, 48, r_out=1.2, z_sigma=5e-4, pack=True, tile=512)
 
 
 def test_ring_1m_ten_steps_rebuilt_every_step():
