@@ -248,3 +248,31 @@ def test_packed_monitor_trajectory_matches_oracle(torch_cuda):
     for k, f in enumerate(("x", "y", "z", "vx", "vy", "vz")):
         assert np.max(np.abs(dev[f].cpu().numpy() - ref[k])) < 1e-10, f
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_packed_groups_on_cylindrical_tree(torch_cuda, precision):
+    """Packing on a tree built in cylindrical coordinates (Sec. 4.3): packs,
+    boxes, lists and forces against the oracle."""
+    torch = torch_cuda
+    from paper_1907_02289_amd import bh
+    _log(f"[gpu] packed groups, cylindrical tree, ring n=30000 seed 43, precision {precision}")
+    s = inputs.ring(30000, 43, r_out=1.2, z_sigma=5e-4)
+    r_ref, theta, eps, n_grp = 1.1, 0.4, 1e-4, 200
+    st = oracle.BHState(s.x, s.y, s.z, s.m, theta, 8, n_grp, cyl_r=r_ref, pack=True)
+    assert st.gnode.size < oracle.BHState(s.x, s.y, s.z, s.m, theta, 8, n_grp, cyl_r=r_ref).gnode.size
+    ctx = bh.Context(theta=theta, eps=eps, n_group=n_grp, precision=precision, cyl_radius=r_ref, pack_groups=True)
+    ctx.build_tree([bh.to_device(s)])
+    ctx.make_lists()
+    _compare(ctx, st)
+    out = {k: torch.zeros(s.n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az")}
+    ctx.forces([out])
+    torch.cuda.synchronize()
+    ax, ay, az, _, mag = st.accel(s.x, s.y, s.z, s.m, eps)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    err = np.sqrt((g["ax"] - ax) ** 2 + (g["ay"] - ay) ** 2 + (g["az"] - az) ** 2)
+    if precision == 0:
+        assert np.all(err <= 1e-12 * mag), f"max err/mag {np.max(err / mag)}"
+    else:
+        fp32_bars(err / np.sqrt(ax ** 2 + ay ** 2 + az ** 2), "packed groups, cylindrical tree")
+    ctx.close()
