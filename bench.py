@@ -18,13 +18,15 @@ value is a full untimed run from t = 0; the matched run's per-evaluation
 errors are the ones reported.
   tuned:   FP32 interactions on group-relative coordinates; rebuild policy
            (lists reused until the drift monitor asks for a rebuild, at most
-           16 or 4 steps, or rebuilt every 2 steps), group size and force
-           tile chosen by measured time per step at matched error; reuse
-           steps replayed from a HIP graph;
+           4 or 16 steps, or rebuilt every 2 steps), group configuration
+           (size, packed small siblings, tree on Cartesian or cylindrical
+           coordinates) and force tile chosen by measured time per step at
+           matched error; reuse steps replayed from a HIP graph;
   plain:   FP64 interactions, groups <= 64, lists rebuilt every step;
-  learned: the tuned path with the learned opening rule (network trained
-           on the GPU by the library's kernels on separate rings and a
-           Plummer sphere), its budget tau matched the same way.
+  learned: the tuned path (on a Cartesian tree) with the learned opening
+           rule (network trained on the GPU by the library's kernels on
+           separate rings and a Plummer sphere), its budget tau matched the
+           same way.
 The JSON line reports the tuned path's interactions/s (whole job, inputs
 resident in device memory, timed window only) and, alongside, the plain and
 learned paths on the same steps, the collision branch of Eq. (2), the
@@ -48,14 +50,16 @@ PAPER_FLOPS_PER_INTERACTION = 31    # the paper's count for a particle-cell inte
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 TARGET_P99 = 1e-3
+CYL_RADIUS = 1.1                    # mid radius of the benchmark ring (r in [1, 1.2])
 # A candidate of the tuned path's autotuning replaces the incumbent (the first
 # of its list) only when it is faster by more than this fraction: times differ
 # by ~1-2% from one MI355X to another, and the choice should not follow that.
 MARGIN = 0.02
-# group configurations of the tuned path (group size, packed small siblings),
-# each matched along the run and timed; the first is the one the rebuild
-# policy is chosen on
-GROUP_CONFIGS = ((384, True), (256, True), (512, True), (256, False), (384, False), (512, False))
+# group configurations of the tuned path (group size, packed small siblings,
+# tree on cylindrical coordinates around the ring's mid radius), each matched
+# along the run and timed; the first is the one the rebuild policy is chosen on
+GROUP_CONFIGS = ((384, True, True), (384, True, False), (256, True, True), (512, True, True), (256, True, False),
+                 (512, True, False), (384, False, False))
 REUSE_MAX = 16                      # longest list age of the tuned path
 # drift monitor of the tuned path: rebuild when, at some tree level, nodes
 # whose particles moved by more than their side relative to the node's centre
@@ -488,6 +492,8 @@ def main():
     ap.add_argument("--legs", default="tuned,plain,learned,collisions,batched",
                     help="comma-separated legs to run (tuned always runs, unless the batched leg runs alone)")
     ap.add_argument("--n-group", type=int, default=None, help="tuned path group size (default: autotuned)")
+    ap.add_argument("--cyl", choices=("on", "off"), default=None,
+                    help="tuned path: tree on cylindrical coordinates (default: autotuned)")
     ap.add_argument("--pack", choices=("on", "off"), default=None,
                     help="pack small sibling groups, tuned path or (with --legs batched alone) the batched "
                          "workload (default: autotuned)")
@@ -506,7 +512,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
     ap.add_argument("--reuse-configs", default=None,
                     help="reuse study: comma-separated subset of R=1,R=2,R=4,R=8,R=16,drift, or drift:<kappa>:<frac>[:<cap>]; "
-                         "a +pack suffix packs small sibling groups")
+                         "a +pack suffix packs small sibling groups, +cyl builds cylindrical trees")
     ap.add_argument("--reuse-study", action="store_true",
                     help="only the list-reuse study: fixed rebuild intervals and the drift monitor, each matched "
                          "along the run, and their time per step")
@@ -558,16 +564,18 @@ def main():
     # matched along the run (the error at a given theta moves with the group
     # boxes) and timed; last the force tile, a changed choice checked by an
     # error run of its own
-    gcands = [(ng, pk) for ng, pk in GROUP_CONFIGS
-              if args.n_group in (None, ng) and args.pack in (None, "on" if pk else "off")]
+    gcands = [(ng, pk, cy) for ng, pk, cy in GROUP_CONFIGS
+              if args.n_group in (None, ng) and args.pack in (None, "on" if pk else "off")
+              and args.cyl in (None, "on" if cy else "off")]
     if not gcands:
-        gcands = [(args.n_group, args.pack == "on")]
+        gcands = [(args.n_group or 384, args.pack == "on", args.cyl == "on")]
     policies = [pl for pl in POLICIES if args.policy in (None, pl[1])]
     base = r = None
     policy_autotune = []
     th0 = None
     for pname, pkey, pol in policies:
         cand = dict(precision=bh.FP32_REL, n_group=gcands[0][0], pack_groups=gcands[0][1],
+                    cyl_radius=CYL_RADIUS if gcands[0][2] else 0.0,
                     force_tile=args.tile or 512, policy=pname, policy_key=pkey,
                     **{k: (dict(v) if isinstance(v, dict) else v) for k, v in pol.items()})
         rc = None
@@ -591,21 +599,25 @@ def main():
             base_cost = cost
         base, r = cand, rc
     best = None
-    for ng, pk in gcands if len(gcands) > 1 else []:
-        p = dict(base, n_group=ng, pack_groups=pk)
-        rp = r if (ng, pk) == (base["n_group"], base["pack_groups"]) else None
+    best_cart = None           # the fastest Cartesian candidate: the learned rule's geometric reference
+    for ng, pk, cy in gcands if len(gcands) > 1 else []:
+        p = dict(base, n_group=ng, pack_groups=pk, cyl_radius=CYL_RADIUS if cy else 0.0)
+        rp = r if (ng, pk, p["cyl_radius"]) == (base["n_group"], base["pack_groups"], base["cyl_radius"]) else None
+        label = f"n_group={ng}{' packed' if pk else ''}{' cylindrical' if cy else ''}"
         if rp is None and args.theta_tuned is None:
             p["theta"], rp = match_along_run(
-                f"tuned n_group={ng}{' packed' if pk else ''} theta",
+                f"tuned {label} theta",
                 lambda th: error_run(bh, w, dev0, judge, dict(p, theta=th), n_evals, 1 + args.warmup),
                 base["theta_first_eval"], 2.0, THETA_FLOOR, guess=base["theta"])
         t = timed(bh, w, dev0, p, args.steps, args.warmup)
         cost = t["wall"] / args.steps * 1e3
-        autotune.append(dict(n_group=ng, pack_groups=pk, force_tile=p["force_tile"], theta=p["theta"],
-                             ms_per_step=cost, max_p99=rp["max"] if rp else None))
-        log(f"[bench] tuned n_group={ng}{' packed' if pk else ''} theta={p['theta']:.5f}: {cost:.2f} ms/step")
+        autotune.append(dict(n_group=ng, pack_groups=pk, cylindrical=cy, force_tile=p["force_tile"],
+                             theta=p["theta"], ms_per_step=cost, max_p99=rp["max"] if rp else None))
+        log(f"[bench] tuned {label} theta={p['theta']:.5f}: {cost:.2f} ms/step")
         if best is None or cost < best[0] * (1.0 - MARGIN):
             best = (cost, p, rp)
+        if not cy and (best_cart is None or cost < best_cart[0]):
+            best_cart = (cost, p)
     if best is not None:
         _, base, r = best
     p = base
@@ -614,8 +626,8 @@ def main():
         t0 = best[0] if best else timed(bh, w, dev0, p, args.steps, args.warmup)["wall"] / args.steps * 1e3
         t = timed(bh, w, dev0, q, args.steps, args.warmup)
         cost = t["wall"] / args.steps * 1e3
-        autotune.append(dict(n_group=q["n_group"], pack_groups=q["pack_groups"], force_tile=q["force_tile"],
-                             theta=q["theta"], ms_per_step=cost, max_p99=None))
+        autotune.append(dict(n_group=q["n_group"], pack_groups=q["pack_groups"], cylindrical=q["cyl_radius"] > 0,
+                             force_tile=q["force_tile"], theta=q["theta"], ms_per_step=cost, max_p99=None))
         log(f"[bench] tuned tile={q['force_tile']}: {cost:.2f} ms/step (tile {p['force_tile']}: {t0:.2f})")
         if cost < t0 * (1.0 - MARGIN):
             p = q
@@ -646,16 +658,24 @@ def main():
                 THETA_FLOOR, guess=guess)
         paths["plain"] = dict(p, run=r)
 
-    # ---- learned opening rule on the tuned configuration
+    # ---- learned opening rule on the tuned configuration (on a Cartesian
+    # tree: the learned rule does not walk cylindrical ones; then the fastest
+    # Cartesian candidate is its geometric reference, timed as well)
+    geo_ref = None
     if "learned" in legs:
         tp = paths["tuned"]
+        if tp.get("cyl_radius", 0.0) > 0.0:
+            geo_ref = dict(best_cart[1]) if best_cart else dict(tp, cyl_radius=0.0)
+            geo_ref.pop("run", None)
+            paths["geometric_reference"] = dict(geo_ref, run=None)
+        lbase = geo_ref or tp
         lo, hi = LEARNED_BAND
         t = time.perf_counter()
-        weights, n_pairs, mse = train_learned(bh, inputs, w, tp["n_group"], tp["theta"])
+        weights, n_pairs, mse = train_learned(bh, inputs, w, lbase["n_group"], lbase["theta"])
         t_train = time.perf_counter() - t
         log(f"[bench] learned: {n_pairs} training pairs, mse {mse:.3f}, {t_train:.1f} s")
-        p = dict(tp, learned=dict(criterion=bh.LEARNED, theta_min=lo, theta_max=hi, tau=1e-4,
-                                  budget_min=args.learned_budget == "min"), weights=weights)
+        p = dict(lbase, learned=dict(criterion=bh.LEARNED, theta_min=lo, theta_max=hi, tau=1e-4,
+                                     budget_min=args.learned_budget == "min"), weights=weights)
         p.pop("run", None)
         if args.tau_learned is not None:
             p["learned"]["tau"] = args.tau_learned
@@ -667,7 +687,7 @@ def main():
             tau0 = first_eval_tau(bh, w, dev0, judge, p)
             # first guess: the error grows along the run as it did for the
             # tuned path's theta; p99 goes about as tau^(1/2)
-            grow = (tp["theta_first_eval"] / tp["theta"]) ** 2 if "theta_first_eval" in tp else 1.0
+            grow = (tp["theta_first_eval"] / lbase["theta"]) ** 2 if "theta_first_eval" in tp else 1.0
             tau, r = match_along_run("learned tau", run_tau, tau0, 0.5, 1e-14, guess=tau0 / grow ** 2)
             p["learned"]["tau"] = tau
             p["tau_first_eval"] = tau0
@@ -675,7 +695,7 @@ def main():
 
     # ---- timed runs (same start, warm-up and steps for every path)
     res = {}
-    for name in ("tuned", "plain", "learned"):
+    for name in ("tuned", "plain", "learned", "geometric_reference"):
         if name in paths:
             res[name] = timed(bh, w, dev0, paths[name], args.steps, args.warmup)
             log(f"[bench] {name}: {res[name]}")
@@ -700,6 +720,7 @@ def main():
     def path_record(name):
         p, r, t = paths[name], paths[name]["run"], res[name]
         rec = dict(theta=p["theta"], n_group=p["n_group"], pack_groups=p.get("pack_groups", False),
+                   tree="cylindrical, r_ref %g" % p["cyl_radius"] if p.get("cyl_radius", 0.0) > 0 else "cartesian",
                    force_tile=p.get("force_tile", 512),
                    s_per_step=t["wall"] / args.steps,
                    interactions_per_s=t["interactions"] / t["wall"],
@@ -732,6 +753,7 @@ def main():
             "workload": workload, "n_particles": n, "eps": w.eps, "dt": w.dt,
             "step": "one kick-drift-kick step (one force evaluation, tree and list builds as they fall)",
             "theta_tuned": tp["theta"], "n_group": tp["n_group"], "pack_groups": tp["pack_groups"],
+            "tree": "cylindrical, r_ref %g" % tp["cyl_radius"] if tp.get("cyl_radius", 0.0) > 0 else "cartesian",
             "force_tile": tp["force_tile"],
             "rebuild": (f"drift monitor {tp['drift']}, at most every {tp['rebuild_every']} steps" if "drift" in tp
                         else f"every {tp['rebuild_every']} steps"), "positions_and_integration": "f64",
@@ -754,6 +776,7 @@ def main():
         "stages_ms_last": tu["stages"],
         "reproduce_without_matching": (f"--steps {args.steps} --warmup {args.warmup} --n-group {tp['n_group']} "
                                        f"--pack {'on' if tp['pack_groups'] else 'off'} "
+                                       f"--cyl {'on' if tp.get('cyl_radius', 0.0) > 0 else 'off'} "
                                        f"--tile {tp['force_tile']} --policy {tp['policy_key']} "
                                        f"--theta-tuned {tp['theta']!r}"
                                        + (f" --theta-plain {paths['plain']['theta']!r}" if "plain" in paths else "")
@@ -778,6 +801,11 @@ def main():
                   training_mse=lp["training_mse"], training_s=lp["training_s"],
                   interactions_vs_geometric=lr["interactions_per_force_eval"] / per_launch,
                   s_per_step_vs_geometric=lr["s_per_step"] / out["s_per_step"])
+        if "geometric_reference" in res:
+            gr = path_record("geometric_reference")
+            lr.update(geometric_reference=gr,
+                      interactions_vs_geometric=lr["interactions_per_force_eval"] / gr["interactions_per_force_eval"],
+                      s_per_step_vs_geometric=lr["s_per_step"] / gr["s_per_step"])
         if "plain" in out:
             lr["speedup_vs_plain_s_per_step"] = out["plain"]["s_per_step"] / lr["s_per_step"]
         out["learned"] = lr
@@ -813,10 +841,13 @@ def reuse_study(bh, w, dev0, judge, n, args):
     configs.append(("drift", dict(rebuild_every=REUSE_MAX, drift=dict(DRIFT))))
     if args.reuse_configs:
         # names from the list above, or drift:<reuse_drift>:<reuse_frac> for another monitor setting
-        # a "+pack" suffix packs small sibling groups
+        # suffixes: "+pack" packs small sibling groups, "+cyl" builds the tree
+        # on cylindrical coordinates around the ring's mid radius
         chosen = []
         for name in args.reuse_configs.split(","):
-            base, pack = (name[:-5], True) if name.endswith("+pack") else (name, False)
+            base, *suffix = name.split("+")
+            if set(suffix) - {"pack", "cyl"}:
+                raise SystemExit(f"unknown suffix in {name}")
             if base.startswith("drift:"):
                 parts = base.split(":")[1:]
                 k, f = float(parts[0]), float(parts[1])
@@ -824,8 +855,10 @@ def reuse_study(bh, w, dev0, judge, n, args):
                 extra = dict(rebuild_every=cap, drift=dict(reuse_drift=k, reuse_frac=f))
             else:
                 extra = next(dict(c[1]) for c in configs if c[0] == base)
-            if pack:
+            if "pack" in suffix:
                 extra["pack_groups"] = True
+            if "cyl" in suffix:
+                extra["cyl_radius"] = CYL_RADIUS
             chosen.append((name, extra))
         configs = chosen
     th0 = None

@@ -1,8 +1,9 @@
 """Parity at the full sizes of the workloads, on sampled outputs: the 2^20
 ring (FP32 interactions, groups <= 256) at t = 0 and along 10 steps rebuilt
 every step; the 2^24 ring in the benchmark's launch configuration (FP32,
-packed groups <= 384, 512-source tiles, theta 0.0846, the value matched
-along the benchmark's run); the 64 batched Plummer spheres (2.2M particles,
+tree on cylindrical coordinates around r = 1.1, packed groups <= 384,
+512-source tiles, theta 0.0865, the value matched along the benchmark's
+run); the 64 batched Plummer spheres (2.2M particles,
 autotuned group size, 20 steps).  Keys, permutation and node arrays are compared in
 full; lists and forces for a random sample of groups, against the oracle
 walking those groups and evaluating their lists in FP64."""
@@ -36,7 +37,7 @@ def _subset_lists(pc_off, pc, pp_off, pp, sel):
 
 
 def _check(ctx, x, y, z, m, theta, eps, n_grp, n_sample_groups, seed, gx, gy, gz, central_mass=0.0,
-           resorted=False, pack=False):
+           resorted=False, pack=False, cyl_r=0.0):
     """The oracle's full build of (x, y, z, m) against the context's keys,
     permutation, nodes, moments, groups and group boxes; the lists and FP32
     forces of a random sample of groups against the oracle walking those
@@ -46,7 +47,7 @@ def _check(ctx, x, y, z, m, theta, eps, n_grp, n_sample_groups, seed, gx, gy, gz
     order rather than the caller's; the permutation is then checked to sort
     the keys, and the oracle takes the same order.  Returns the permutation and
     the sorted-order particle indices of the sampled groups."""
-    _, _, _, key = oracle.keys(x, y, z)
+    _, _, _, key = oracle.keys_cyl(x, y, z, cyl_r) if cyl_r > 0 else oracle.keys(x, y, z)
     perm = oracle.sort_perm(key)
     skey = key[perm]
     np.testing.assert_array_equal(ctx.export("keys"), skey)
@@ -82,7 +83,7 @@ def _check(ctx, x, y, z, m, theta, eps, n_grp, n_sample_groups, seed, gx, gy, gz
     np.testing.assert_array_equal(cen, gcen)
     ns = min(n_sample_groups, g.size)
     sel = np.sort(np.random.default_rng(seed).choice(g.size, ns, replace=False))
-    o_pc_off, o_pc, o_pp_off, o_pp = oracle.lists(gbox[sel], t, theta)
+    o_pc_off, o_pc, o_pp_off, o_pp = oracle.lists(gbox[sel], t, theta, oracle.CYL_PERIOD if cyl_r > 0 else 0)
     pc_off, pc, pp_off, pp = ctx.export("lists")
     a, b, c, d = _subset_lists(pc_off, pc, pp_off, pp, sel)
     np.testing.assert_array_equal(a, o_pc_off)
@@ -101,14 +102,15 @@ def _check(ctx, x, y, z, m, theta, eps, n_grp, n_sample_groups, seed, gx, gy, gz
     return perm, idx
 
 
-def _run(n, seed, theta, eps, n_grp, n_sample_groups, r_out=1.1, z_sigma=1e-3, pack=False, tile=0):
+def _run(n, seed, theta, eps, n_grp, n_sample_groups, r_out=1.1, z_sigma=1e-3, pack=False, tile=0, cyl_r=0.0):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1907_02289_amd import bh
     s = inputs.ring(n, seed, r_out=r_out, z_sigma=z_sigma, central_mass=1.0)
     _log(f"[gpu] fullsize n={n} theta={theta} groups <= {n_grp}{' packed' if pack else ''}")
-    ctx = bh.Context(theta=theta, eps=eps, n_group=n_grp, precision=bh.FP32_REL, pack_groups=pack, force_tile=tile)
+    ctx = bh.Context(theta=theta, eps=eps, n_group=n_grp, precision=bh.FP32_REL, pack_groups=pack, force_tile=tile,
+                     cyl_radius=cyl_r)
     dev = bh.to_device(s)
     ctx.build_tree([dev])
     ctx.make_lists()
@@ -117,7 +119,7 @@ def _run(n, seed, theta, eps, n_grp, n_sample_groups, r_out=1.1, z_sigma=1e-3, p
     torch.cuda.synchronize()
     perm = ctx.export("perm")
     gx, gy, gz = (out[k].cpu().numpy()[perm] for k in ("ax", "ay", "az"))
-    _check(ctx, s.x, s.y, s.z, s.m, theta, eps, n_grp, n_sample_groups, seed, gx, gy, gz, pack=pack)
+    _check(ctx, s.x, s.y, s.z, s.m, theta, eps, n_grp, n_sample_groups, seed, gx, gy, gz, pack=pack, cyl_r=cyl_r)
     ctx.close()
 
 
@@ -127,7 +129,7 @@ def test_ring_1m_fp32_groups256():
 
 @pytest.mark.slow
 def test_ring_16m_benchmark_configuration():
-    _run(1 << 24, 3, 0.08457338666050794, 1e-4, 384, 48, r_out=1.2, z_sigma=5e-4, pack=True, tile=512)
+    _run(1 << 24, 3, 0.08650261852548162, 1e-4, 384, 48, r_out=1.2, z_sigma=5e-4, pack=True, tile=512, cyl_r=1.1)
 
 
 def test_ring_1m_ten_steps_rebuilt_every_step():
