@@ -328,12 +328,13 @@ def timed(bh, w, dev0, p, steps, warmup):
     return res
 
 
-def train_learned(bh, inputs, w, n_group, theta):
+def train_learned(bh, inputs, w, n_group, theta, band=LEARNED_BAND):
     """The learned rule's network, trained by the library's kernels on pairs
     it collects from separate 1M-particle rings and a Plummer sphere
-    (seeds 100-102, disjoint from the benchmark ring's)."""
+    (seeds 100-102, disjoint from the benchmark ring's); training pairs are
+    the (group, node) pairs of the band."""
     import torch
-    lo, hi = LEARNED_BAND
+    lo, hi = band
     tr = bh.Context(theta=theta, eps=w.eps, precision=bh.FP32_REL, n_group=n_group, criterion=bh.LEARNED,
                     theta_min=lo, theta_max=hi, tau=1e-4)
     for sysm in (inputs.ring(1 << 20, 100, central_mass=1.0),
@@ -505,6 +506,8 @@ def main():
     ap.add_argument("--theta-tuned", type=float, default=None, help="skip matching, use this theta (tuned path)")
     ap.add_argument("--theta-plain", type=float, default=None, help="skip matching, use this theta (plain path)")
     ap.add_argument("--tau-learned", type=float, default=None, help="skip matching, use this tau (learned path)")
+    ap.add_argument("--learned-band", type=float, nargs=2, default=LEARNED_BAND, metavar=("LO", "HI"),
+                    help="learned rule: the band of side/distance in which the network decides")
     ap.add_argument("--learned-budget", choices=("mean", "min"), default="mean",
                     help="the learned rule's budget scale A_g: mean or smallest |a| of a group's particles")
     ap.add_argument("--no-error-runs", action="store_true",
@@ -669,9 +672,9 @@ def main():
             geo_ref.pop("run", None)
             paths["geometric_reference"] = dict(geo_ref, run=None)
         lbase = geo_ref or tp
-        lo, hi = LEARNED_BAND
+        lo, hi = args.learned_band
         t = time.perf_counter()
-        weights, n_pairs, mse = train_learned(bh, inputs, w, lbase["n_group"], lbase["theta"])
+        weights, n_pairs, mse = train_learned(bh, inputs, w, lbase["n_group"], lbase["theta"], (lo, hi))
         t_train = time.perf_counter() - t
         log(f"[bench] learned: {n_pairs} training pairs, mse {mse:.3f}, {t_train:.1f} s")
         p = dict(lbase, learned=dict(criterion=bh.LEARNED, theta_min=lo, theta_max=hi, tau=1e-4,
@@ -795,7 +798,7 @@ def main():
     if "learned" in paths:
         lr = path_record("learned")
         lp = paths["learned"]
-        lr.update(tau=lp["learned"]["tau"], tau_first_eval=lp.get("tau_first_eval"), band=list(LEARNED_BAND),
+        lr.update(tau=lp["learned"]["tau"], tau_first_eval=lp.get("tau_first_eval"), band=list(args.learned_band),
                   budget="min" if lp["learned"]["budget_min"] else "mean",
                   training_pairs=lp["training_pairs"],
                   training_mse=lp["training_mse"], training_s=lp["training_s"],
