@@ -449,35 +449,45 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "repeats": 3}))
 
 
-def cpu_baseline(system, theta, n_grp, eps, n_sample_groups=16384, seed=0):
-    """The oracle on the host cores: full tree build of the same ring, then
-    walk + forces for a random sample of groups; interactions of the sample
-    over the time of the sample's work (the build prorated to the sample's
-    share of groups)."""
+def cpu_baseline(system, theta, n_grp, eps, n_sample_groups=16384, seed=0, cyl_r=0.0, pack=False):
+    """The oracle on the host cores, in the tuned path's tree and group
+    configuration: full tree build of the same ring, then walk + forces for
+    a random sample of groups; interactions of the sample over the time of
+    the sample's work (the build prorated to the sample's share of groups)."""
     import oracle
     t0 = time.perf_counter()
-    _, _, _, key = oracle.keys(system.x, system.y, system.z)
+    if cyl_r > 0.0:
+        _, _, _, key = oracle.keys_cyl(system.x, system.y, system.z, cyl_r)
+    else:
+        _, _, _, key = oracle.keys(system.x, system.y, system.z)
     perm = oracle.sort_perm(key)
     skey = key[perm]
     t = oracle.tree(skey, 8)
     xs, ys, zs, ms = (a[perm] for a in (system.x, system.y, system.z, system.m))
     mom = oracle.moments(t, xs, ys, zs, ms)
-    g = oracle.groups(t, n_grp)
-    gbox, _ = oracle.group_boxes(g, t, skey, xs, ys, zs)
+    if pack:
+        g, gbeg, gcnt = oracle.groups_packed(t, n_grp)
+    else:
+        g = oracle.groups(t, n_grp)
+        gbeg, gcnt = t["begin"][g], t["count"][g]
+    gbox, _ = oracle.group_boxes(np.arange(g.size, dtype=np.uint32), dict(begin=gbeg, count=gcnt), skey,
+                                 xs, ys, zs)
     t_build = time.perf_counter() - t0
     rng = np.random.default_rng(seed)
     sel = np.sort(rng.choice(g.size, min(n_sample_groups, g.size), replace=False))
     t1 = time.perf_counter()
-    pc_off, pc, pp_off, pp = oracle.lists(gbox[sel], t, theta)
-    oracle.forces(g[sel], t, xs, ys, zs, ms, mom, pc_off, pc, pp_off, pp, eps)
+    pc_off, pc, pp_off, pp = oracle.lists(gbox[sel], t, theta, oracle.CYL_PERIOD if cyl_r > 0.0 else 0)
+    oracle.forces(g[sel], t, xs, ys, zs, ms, mom, pc_off, pc, pp_off, pp, eps, granges=(gbeg[sel], gcnt[sel]))
     t_sample = time.perf_counter() - t1
     cnt = t["count"].astype(np.int64)
     pp_len = np.array([cnt[pp[pp_off[k]:pp_off[k + 1]]].sum() for k in range(sel.size)])
-    inter = int(np.sum(cnt[g[sel]] * (pp_len + np.diff(pc_off))))
+    inter = int(np.sum(gcnt[sel].astype(np.int64) * (pp_len + np.diff(pc_off))))
     share = sel.size / g.size
     t_total = t_sample + t_build * share
+    tree = f"cylindrical tree (r_ref {cyl_r:g})" if cyl_r > 0.0 else "Cartesian tree"
     return dict(value=inter / t_total, unit="interactions/s", cores=oracle.n_threads(), kind="oracle",
-                sample=(f"16M ring at t = 0, theta={theta:.4f}, n_grp={n_grp}, Cartesian tree: oracle tree build "
+                sample=(f"16M ring at t = 0, theta={theta:.4f}, n_grp={n_grp}{', packed' if pack else ''}, "
+                        f"{tree}: oracle tree build "
                         f"of all {system.n} particles ({t_build:.1f} s, prorated {share:.4f} of groups) + walk and "
                         f"FP64 forces of {sel.size} random groups ({t_sample:.2f} s, {inter} interactions)"),
                 seconds=t_build + t_sample)
@@ -825,7 +835,8 @@ def main():
         out["batched"] = bat
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(sysm, tp["theta"], tp["n_group"], w.eps)
+        out["cpu_baseline"] = cpu_baseline(sysm, tp["theta"], tp["n_group"], w.eps, cyl_r=tp.get("cyl_radius", 0.0),
+                                           pack=tp.get("pack_groups", False))
     print(json.dumps(out), flush=True)
 
 
