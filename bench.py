@@ -416,8 +416,12 @@ def batched_leg(bh, inputs, steps, pack=None):
 
 
 def force_source_digest():
-    src = os.path.join(ROOT, "paper_1907_02289_amd", "csrc", "bh_force.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    """Digest of the force kernel's source and of the walk's (which sets the
+    order the kernel takes its groups in)."""
+    h = hashlib.sha256()
+    for f in ("bh_force.hip", "bh_walk.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1907_02289_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload, n_group, theta):

@@ -351,14 +351,19 @@ __global__ void k_walk_reset(DevState d) {
 }
 
 // Work order for the force kernel: groups by descending interaction count
-// (the list-length ordering of the paper's load balance, Sec. 4.6).
+// (the list-length ordering of the paper's load balance, Sec. 4.6), in
+// classes of half an octave of cost; inside a class, ascending group id,
+// i.e. along the Morton curve, so that the groups in flight at one time are
+// neighbours whose lists share most of their sources in L2.  Key: class
+// (7 bits, largest cost first) above the group id (32 bits).
 __global__ void k_order_keys(DevState d, uint64_t *key, uint32_t *val) {
     const uint32_t ng = d.cnt->n_groups;
     uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += stride) {
-        unsigned long long c = d.g_cost[g];
-        const unsigned long long cap = (1ull << 40) - 1;
-        key[g] = cap - (c < cap ? c : cap);
+        const unsigned long long c = d.g_cost[g];
+        uint32_t cls = c ? (uint32_t)(2.0 * log2((double)c)) : 0u;
+        cls = cls < 127u ? cls : 127u;
+        key[g] = ((unsigned long long)(127u - cls) << 32) | (unsigned long long)g;
         val[g] = g;
     }
 }

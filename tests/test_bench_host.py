@@ -47,8 +47,9 @@ def test_traffic_record_lookup(tmp_path, monkeypatch):
     digest = bench.force_source_digest()
     (tmp_path / "profiles").mkdir()
     (tmp_path / "paper_1907_02289_amd" / "csrc").mkdir(parents=True)
-    src = os.path.join(bench.ROOT, "paper_1907_02289_amd", "csrc", "bh_force.hip")
-    (tmp_path / "paper_1907_02289_amd" / "csrc" / "bh_force.hip").write_bytes(open(src, "rb").read())
+    for f in ("bh_force.hip", "bh_walk.hip"):
+        src = os.path.join(bench.ROOT, "paper_1907_02289_amd", "csrc", f)
+        (tmp_path / "paper_1907_02289_amd" / "csrc" / f).write_bytes(open(src, "rb").read())
     rec = dict(workload="ring16_kdk1+2", n_group=384, theta=0.0842, kernel_source_sha256_16=digest,
                hbm_bytes_per_launch=123.0)
     (tmp_path / "profiles" / "force_kernel_traffic.json").write_text(json.dumps([rec]))
@@ -57,12 +58,12 @@ def test_traffic_record_lookup(tmp_path, monkeypatch):
     assert bench.measured_traffic("ring16_kdk1+2", 256, 0.0842) is None
     assert bench.measured_traffic("ring16_kdk1+2", 384, 0.0843) is None
     assert bench.measured_traffic("ring16_kdk5+20", 384, 0.0842) is None
-    (tmp_path / "paper_1907_02289_amd" / "csrc" / "bh_force.hip").write_bytes(b"// changed kernel\n")
+    (tmp_path / "paper_1907_02289_amd" / "csrc" / "bh_walk.hip").write_bytes(b"// changed work order\n")
     assert bench.measured_traffic("ring16_kdk1+2", 384, 0.0842) is None
 
 
 def test_committed_traffic_record_matches_the_force_kernel_source():
-    """The committed record was taken on the current force-kernel source (a
-    changed kernel needs new counter runs)."""
+    """The committed record was taken on the current force-kernel and walk
+    sources (a changed kernel or work order needs new counter runs)."""
     recs = json.load(open(os.path.join(bench.ROOT, "profiles", "force_kernel_traffic.json")))
     assert any(r["kernel_source_sha256_16"] == bench.force_source_digest() for r in recs)
