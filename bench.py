@@ -577,10 +577,10 @@ def main():
 
     # ---- tuned path: first the rebuild policy (drift monitor or a fixed
     # interval), each with its own theta matched along the run, by measured
-    # time per step; then the group configuration (size, packing), each
-    # matched along the run (the error at a given theta moves with the group
-    # boxes) and timed; last the force tile, a changed choice checked by an
-    # error run of its own
+    # time per step; then the group configuration (size, packing, Cartesian
+    # or cylindrical tree), each matched along the run (the error at a given
+    # theta moves with the group boxes and the tree) and timed; last the force
+    # tile, a changed choice checked by an error run of its own
     gcands = [(ng, pk, cy) for ng, pk, cy in GROUP_CONFIGS
               if args.n_group in (None, ng) and args.pack in (None, "on" if pk else "off")
               and args.cyl in (None, "on" if cy else "off")]
